@@ -1,0 +1,261 @@
+/*
+ * lms.h -- C ABI of the MI355X (gfx950) micro-batch stream operator library.
+ *
+ * LMStream (Lee & Park, arXiv 2111.04289) runs a streaming query as a chain of
+ * operations over each admitted micro-batch (Sec. III-A, Fig. 3; problem
+ * statement Sec. III-B, Eq. 1-5).  The operations whose GPU functions this
+ * library provides are the rows of Table II that touch the data of a single
+ * micro-batch: Filtering, Projection, Aggregation (Hash) over tumbling or
+ * sliding event-time windows (window slide semantics of Table I, SlideTime,
+ * with 0 meaning a tumbling window; Expand is realised by pane
+ * decomposition) and Join (Hash) of the stream against a static table.
+ * lms_plan implements the MapDevice placement (Algorithm 2) with the device
+ * cost model of Eq. 7-9.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Column data pointers in lms_col are DEVICE pointers (hipMalloc'd or
+ *    torch CUDA tensors); every other pointer argument is a HOST pointer unless
+ *    its name starts with d_.  All buffers are owned by the caller; the library
+ *    keeps no pointer after a call returns, except the opaque lms_join_table,
+ *    which it owns until lms_join_free.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are stream-ordered and asynchronous: they validate arguments on the
+ *    host, enqueue kernels and return.  Results and device counts are valid
+ *    once the caller has synchronised the stream.
+ *  - Return value: LMS_OK (0) or a negative LMS_E* code for errors detected on
+ *    the host (nothing is enqueued then).  lms_last_error() gives a
+ *    thread-local message for the last failing call on this thread.
+ *  - d_count arguments point to a DEVICE array of 2 int64: [0] receives the
+ *    number of result rows the operation produced (also when it exceeds the
+ *    capacity: then only `cap` rows are written and the caller may retry with a
+ *    larger capacity), [1] receives a device-detected status (0 or a negative
+ *    LMS_E* code, e.g. LMS_ECAPACITY).  Results are valid only if [1] == 0.
+ *  - Workspace: scratch device memory supplied by the caller, at least the
+ *    size that the matching *_workspace() query returns.  The library performs
+ *    no device allocation on the per-batch path.  Two calls that overlap in
+ *    time must not share a workspace.
+ *  - Re-entrancy: calls on different streams with different workspaces may
+ *    run concurrently.
+ */
+#ifndef LMS_H
+#define LMS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LMS_ABI_VERSION 1
+
+/* Status codes. */
+#define LMS_OK 0
+#define LMS_EINVAL -1    /* bad argument: null pointer, bad dtype/column index, slide > len, cap too small ... */
+#define LMS_EHIP -2      /* a HIP runtime call or kernel launch failed */
+#define LMS_ENOMEM -3    /* workspace too small or a library allocation failed */
+#define LMS_ECAPACITY -4 /* device: a key has more distinct panes than one partition table holds */
+#define LMS_ERANGE -5    /* device: an event time lies more than 2^31 panes away from the batch's first row */
+
+typedef void* lms_stream; /* hipStream_t */
+
+typedef enum { LMS_I32 = 0, LMS_I64 = 1, LMS_F32 = 2, LMS_F64 = 3 } lms_dtype;
+
+/* Comparison of a predicate.  Integer columns compare as int64 against ival;
+ * floating columns compare as double against fval with IEEE semantics (a NaN
+ * row satisfies only LMS_NE). */
+typedef enum { LMS_LT = 0, LMS_LE = 1, LMS_GT = 2, LMS_GE = 3, LMS_EQ = 4, LMS_NE = 5 } lms_cmp;
+
+/* Aggregate functions of the hash aggregation (Table II "Aggregation (Hash)";
+ * the query shapes of Table III use SUM and AVG).  COUNT counts the rows of the
+ * group; SUM/MIN/MAX need an integer input and give int64 (SUM wraps modulo
+ * 2^64); AVG accepts any numeric input and gives the double quotient of the
+ * double sum by the count. */
+typedef enum { LMS_COUNT = 0, LMS_SUM = 1, LMS_MIN = 2, LMS_MAX = 3, LMS_AVG = 4 } lms_aggfn;
+
+/* One column: `data` is a device pointer to nrows values of `dtype`. */
+typedef struct {
+  void* data;
+  int32_t dtype;
+  int32_t reserved;
+} lms_col;
+
+/* A micro-batch, or one partition of it (Table I: Part_(i,j)), as columns of
+ * equal length (structure of arrays). */
+typedef struct {
+  const lms_col* cols; /* host array of ncols column descriptors */
+  int32_t ncols;
+  int32_t reserved;
+  int64_t nrows;
+} lms_batch;
+
+/* Predicate `cols[col] op constant`; a list of predicates is a conjunction. */
+typedef struct {
+  int32_t col;
+  int32_t op; /* lms_cmp */
+  int64_t ival;
+  double fval;
+} lms_pred;
+
+/* Projection: a new integer column v = src * mul + add, evaluated in 64-bit
+ * two's complement and truncated to the source column's width (int32 sources
+ * wrap modulo 2^32).  Only integer sources are accepted. */
+typedef struct {
+  int32_t src;
+  int32_t reserved;
+  int64_t mul;
+  int64_t add;
+} lms_proj;
+
+/* Event-time window (Table I SlideTime; CQL [range len slide slide] of
+ * Table III).  Window starts are origin + k*slide for every integer k; a row
+ * with event time ts belongs to each window with start <= ts < start + len.
+ * slide == 0 means a tumbling window (slide = len).  Requires
+ * 0 < slide <= len and both < 2^31.  Event times must lie within +-2^62. */
+typedef struct {
+  int32_t ts_col; /* integer column holding the event time */
+  int32_t reserved;
+  int64_t len;
+  int64_t slide;
+  int64_t origin;
+} lms_window;
+
+/* One aggregate: fn over column `col`, where col indexes the input columns
+ * followed by the projected columns (ncols + j is projection j).  col is
+ * ignored for LMS_COUNT. */
+typedef struct {
+  int32_t fn; /* lms_aggfn */
+  int32_t col;
+} lms_agg;
+
+/* Output of lms_window_agg: one row per (key, window) holding >= 1 row that
+ * passed the predicates.  Device columns of capacity `cap`: key (int64, the
+ * key column's value widened), window start (int64), then aggs[a] is int64 for
+ * COUNT/SUM/MIN/MAX and double for AVG.  Row order is unspecified. */
+typedef struct {
+  int64_t* key;
+  int64_t* wstart;
+  void* const* aggs; /* host array of nagg device pointers */
+  int64_t cap;
+} lms_groups;
+
+/* Library and ABI information. */
+int lms_abi_version(void);
+const char* lms_last_error(void);
+
+/* ---- Filtering + Projection (Table II rows "Filtering" and "Projection";
+ * the select-project query of Sec. II-C / III-D) --------------------------
+ * Keeps the rows of `in` for which every predicate holds, in input order, and
+ * writes for each kept row the input columns listed in keep[0..nkeep) followed
+ * by the projections projs[0..nproj).  out->ncols must equal nkeep + nproj,
+ * out column j must have the dtype of its source and room for in->nrows rows
+ * (the provable bound; no device-side capacity check is needed).
+ * d_count[0] receives the number of kept rows.
+ * Workspace: lms_filter_project_workspace(in->nrows) bytes. */
+size_t lms_filter_project_workspace(int64_t nrows);
+int lms_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred, const int32_t* keep,
+                       int32_t nkeep, const lms_proj* projs, int32_t nproj, const lms_batch* out,
+                       int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream);
+
+/* ---- Windowed hash group-by (Table II "Aggregation (Hash)" and "Expand";
+ * windows per Table I SlideTime and the range/slide clauses of Table III) ---
+ * Groups the rows that pass the predicates by (cols[key_col], window) and
+ * computes aggs[0..nagg) per group.  The key column must be integer.  Output
+ * rows go to `out` (see lms_groups); d_count[0] receives the number of groups,
+ * of which min(count, out->cap) are written.  d_count[1] is LMS_ECAPACITY if
+ * a single key holds more distinct panes (pane = gcd(len, slide)) than one
+ * workgroup table can hold (see lms_window_agg_pane_limit), LMS_ERANGE if an
+ * event time is more than 2^31 panes away from the first row's.
+ * Workspace: lms_window_agg_workspace() with the same arguments. */
+size_t lms_window_agg_workspace(const lms_batch* in, int32_t key_col, const lms_window* w, const lms_agg* aggs,
+                                int32_t nagg);
+int64_t lms_window_agg_pane_limit(int32_t nagg);
+int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs, int32_t nproj,
+                   int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg, const lms_groups* out,
+                   int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream);
+
+/* ---- Stream-static hash join (Table II "Join (Hash)"; the join of LR1 in
+ * Table III) ---------------------------------------------------------------
+ * lms_join_build hashes the static table `tbl` on integer column key_col and
+ * keeps the int32 column payload_col; it allocates the table (device memory
+ * owned by the library) and enqueues the build on `stream`.
+ * lms_hash_join emits, for every probe row i and every build row j with equal
+ * key, the pair (i, payload_j): out_probe_idx[r] = i, out_payload[r] =
+ * payload_j, grouped by ascending i (pairs of one probe row in unspecified
+ * order).  probe->nrows must be < 2^32.  d_count[0] receives the number of
+ * pairs, of which min(count, cap) are written.  cap >= probe->nrows *
+ * lms_join_max_mult(t) is always enough.
+ * lms_join_max_mult returns the largest number of build rows sharing one key
+ * (it synchronises the build stream).  Workspace:
+ * lms_hash_join_workspace(probe->nrows). */
+typedef struct lms_join_table lms_join_table;
+int lms_join_build(const lms_batch* tbl, int32_t key_col, int32_t payload_col, lms_join_table** out,
+                   lms_stream stream);
+int64_t lms_join_max_mult(lms_join_table* t);
+int64_t lms_join_build_rows(const lms_join_table* t);
+void lms_join_free(lms_join_table* t);
+size_t lms_hash_join_workspace(int64_t nprobe);
+int lms_hash_join(const lms_join_table* t, const lms_batch* probe, int32_t key_col, uint32_t* out_probe_idx,
+                  int32_t* out_payload, int64_t cap, int64_t* d_count, void* workspace, size_t ws_bytes,
+                  lms_stream stream);
+
+/* ---- Device placement (MapDevice, Algorithm 2; cost model Eq. 7-9) -------
+ * Host-only and synchronous.  ops[0..nops) is the operation chain in
+ * execution order (the traversal of the operation DAG, leaf first).  For each
+ * operation o with x = Part / InfPT, Part = batch_bytes / num_cores (Sec.
+ * III-D: the per-core partition size):
+ *   CPU_o = base_o * x (Eq. 7), GPU_o = base_o / x (Eq. 8),
+ *   Trans_o = base_trans * x (Eq. 9);
+ *   Trans is added to GPU_o if o is the first or the last operation or o-1 was
+ *   placed on the CPU, to CPU_o otherwise; o goes to the CPU iff GPU_o > CPU_o.
+ * base_cost <= 0 selects the Table II default of the operation's kind.
+ * out_dev[o] receives LMS_DEV_CPU or LMS_DEV_GPU, out_cost[o] (may be NULL)
+ * the cost of the chosen device including Trans where it was charged.
+ * mode LMS_PLAN_LEARNED uses the learned model `model` (lms_mlp_model) and
+ * falls back to the analytic rule if model is NULL. */
+typedef enum {
+  LMS_OP_AGG = 0,     /* Aggregation (Hash): CPU / 1.0 */
+  LMS_OP_FILTER = 1,  /* Filtering: CPU / 1.0 */
+  LMS_OP_SHUFFLE = 2, /* Shuffling: CPU / 1.0 */
+  LMS_OP_PROJECT = 3, /* Projection: Neutral / 0.9 */
+  LMS_OP_JOIN = 4,    /* Join (Hash): Neutral / 0.9 */
+  LMS_OP_EXPAND = 5,  /* Expand: Neutral / 0.9 */
+  LMS_OP_SCAN = 6,    /* Scan (CSV file): GPU / 0.8 */
+  LMS_OP_SORT = 7     /* Sorting: GPU / 0.8 */
+} lms_opkind;
+typedef enum { LMS_DEV_CPU = 0, LMS_DEV_GPU = 1 } lms_device;
+typedef enum { LMS_PLAN_ANALYTIC = 0, LMS_PLAN_LEARNED = 1 } lms_plan_mode;
+
+typedef struct {
+  int32_t kind; /* lms_opkind */
+  int32_t reserved;
+  double base_cost; /* <= 0: Table II default */
+} lms_op_desc;
+
+typedef struct {
+  int64_t batch_bytes; /* size of the micro-batch in bytes */
+  int32_t num_cores;   /* NumCores (Table I): number of data partitions */
+  int32_t reserved;
+  int64_t rows;          /* rows of the micro-batch */
+  double selectivity;    /* fraction of rows passing the filter */
+  int64_t distinct_keys; /* estimated distinct group keys */
+} lms_batch_stats;
+
+typedef struct {
+  double infpt_bytes; /* InfPT, the inflection point (Sec. III-D; initial 150 KB = 153600) */
+  double base_trans;  /* baseTransCost of Eq. 9 (initial 0.1) */
+  int32_t mode;       /* lms_plan_mode */
+  int32_t reserved;
+  const void* model; /* learned model for LMS_PLAN_LEARNED, else NULL */
+} lms_cost_params;
+
+double lms_table2_base_cost(int32_t kind);
+int lms_plan(const lms_op_desc* ops, int32_t nops, const lms_batch_stats* st, const lms_cost_params* cp,
+             int32_t* out_dev, double* out_cost);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LMS_H */

@@ -200,6 +200,23 @@ int lms_hash_join(const lms_join_table* t, const lms_batch* probe, int32_t key_c
                   int32_t* out_payload, int64_t cap, int64_t* d_count, void* workspace, size_t ws_bytes,
                   lms_stream stream);
 
+/* ---- Kernel tracing ---------------------------------------------------------
+ * Per-launch timing for profiling and for the timing records of the placement
+ * model.  While enabled, every kernel the library launches is bracketed by a
+ * pair of hipEvents recorded on its stream.  lms_trace_read waits for the
+ * recorded events, aggregates them per kernel name into out[0..max_out) and
+ * clears the record; it returns the number of distinct kernels (or a negative
+ * LMS_E* code).  Tracing is process-wide. */
+typedef struct {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+  double min_ms;
+  double max_ms;
+} lms_trace_stat;
+int lms_trace_enable(int32_t on);
+int lms_trace_read(lms_trace_stat* out, int32_t max_out);
+
 /* ---- Device placement (MapDevice, Algorithm 2; cost model Eq. 7-9) -------
  * Host-only and synchronous.  ops[0..nops) is the operation chain in
  * execution order (the traversal of the operation DAG, leaf first).  For each

@@ -1,0 +1,171 @@
+// Filtering + Projection (Table II rows "Filtering" and "Projection"): stable
+// stream compaction of the rows that pass a conjunction of predicates.
+//
+// Three launches: per-tile counts of passing rows, one scan of the tile
+// counts, then a write pass in which every round of TPB consecutive rows gets
+// its output ranks from a wave ballot/prefix and a block prefix, so rows keep
+// their input order without any global atomic.
+#include <algorithm>
+
+#include "lms_internal.h"
+
+namespace lms {
+namespace {
+
+constexpr int kTPB = 256;
+constexpr int kScanThreads = 1024;
+
+struct FpArgs {
+  Query q;
+  int32_t nkeep;
+  int32_t keep[kMaxCols];
+  void* out[kMaxCols + kMaxProjs];
+  int32_t odt[kMaxCols + kMaxProjs];
+  int64_t chunk;
+  int32_t ntiles;
+  int64_t* tile_cnt;
+  int64_t* tile_off;
+  int64_t* d_count;
+};
+
+__global__ __launch_bounds__(kTPB) void k_fp_count(FpArgs a) {
+  __shared__ uint32_t scratch[kTPB / 64 + 1];
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = min(a.q.nrows, lo + a.chunk);
+  uint32_t c = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kTPB) c += row_passes(a.q, i) ? 1u : 0u;
+  c = block_sum<kTPB>(c, scratch);
+  if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_fp_scan(FpArgs a) {
+  __shared__ int64_t total;
+  tile_offsets<kScanThreads>(a.tile_cnt, a.tile_off, a.ntiles, &total);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.d_count[0] = total;
+    a.d_count[1] = 0;
+  }
+}
+
+__device__ __forceinline__ void store_value(void* col, int dt, int64_t r, const Query& q, int src, int64_t i,
+                                            bool is_proj, int pj) {
+  if (is_proj) {
+    const int64_t v = project(q, pj, i);
+    if (dt == LMS_I32) ((int32_t*)col)[r] = (int32_t)v;
+    else ((int64_t*)col)[r] = v;
+    return;
+  }
+  switch (dt) {
+    case LMS_I32: ((int32_t*)col)[r] = ((const int32_t*)q.col[src])[i]; break;
+    case LMS_I64: ((int64_t*)col)[r] = ((const int64_t*)q.col[src])[i]; break;
+    case LMS_F32: ((float*)col)[r] = ((const float*)q.col[src])[i]; break;
+    default: ((double*)col)[r] = ((const double*)q.col[src])[i]; break;
+  }
+}
+
+__global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
+  __shared__ uint32_t scratch[kTPB / 64 + 1];
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = min(a.q.nrows, lo + a.chunk);
+  int64_t run = a.tile_off[blockIdx.x];
+  for (int64_t b = lo; b < hi; b += kTPB) {
+    const int64_t i = b + threadIdx.x;
+    const bool pass = i < hi && row_passes(a.q, i);
+    uint32_t tot;
+    const uint32_t r = block_excl_scan<kTPB>(pass ? 1u : 0u, scratch, &tot);
+    if (pass) {
+      const int64_t o = run + r;
+      for (int j = 0; j < a.nkeep; ++j) store_value(a.out[j], a.odt[j], o, a.q, a.keep[j], i, false, 0);
+      for (int j = 0; j < a.q.nproj; ++j)
+        store_value(a.out[a.nkeep + j], a.odt[a.nkeep + j], o, a.q, a.q.prsrc[j], i, true, j);
+    }
+    run += tot;
+  }
+}
+
+__global__ void k_fp_empty(FpArgs a) {
+  if (threadIdx.x == 0) {
+    a.d_count[0] = 0;
+    a.d_count[1] = 0;
+  }
+}
+
+struct FpPlan {
+  int64_t chunk;
+  int ntiles;
+};
+
+FpPlan fp_plan(int64_t n) {
+  FpPlan p;
+  p.chunk = 4096;
+  while ((n + p.chunk - 1) / p.chunk > 65536) p.chunk *= 2;
+  p.ntiles = (int)((n + p.chunk - 1) / p.chunk);
+  return p;
+}
+
+size_t fp_workspace(int64_t n, FpArgs* a, void* base) {
+  const FpPlan p = fp_plan(n);
+  WsCarver c(base);
+  int64_t* cnt = c.take<int64_t>(std::max(1, p.ntiles));
+  int64_t* off = c.take<int64_t>(std::max(1, p.ntiles));
+  if (a) {
+    a->tile_cnt = cnt;
+    a->tile_off = off;
+  }
+  return c.size();
+}
+
+}  // namespace
+}  // namespace lms
+
+using namespace lms;
+
+extern "C" size_t lms_filter_project_workspace(int64_t nrows) {
+  return nrows < 0 ? 0 : fp_workspace(nrows, nullptr, nullptr);
+}
+
+extern "C" int lms_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred, const int32_t* keep,
+                                  int32_t nkeep, const lms_proj* projs, int32_t nproj, const lms_batch* out,
+                                  int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream) {
+  FpArgs a{};
+  int rc = build_query(in, preds, npred, projs, nproj, &a.q);
+  if (rc) return rc;
+  if (nkeep < 0 || nkeep > kMaxCols) return set_error(LMS_EINVAL, "nkeep %d outside [0, %d]", nkeep, kMaxCols);
+  if (nkeep > 0 && !keep) return set_error(LMS_EINVAL, "keep is NULL");
+  if (!out || out->ncols != nkeep + nproj) return set_error(LMS_EINVAL, "output must have nkeep + nproj columns");
+  if (out->ncols > 0 && !out->cols) return set_error(LMS_EINVAL, "output cols is NULL");
+  if (!d_count) return set_error(LMS_EINVAL, "d_count is NULL");
+  a.nkeep = nkeep;
+  for (int j = 0; j < nkeep; ++j) {
+    if (keep[j] < 0 || keep[j] >= in->ncols) return set_error(LMS_EINVAL, "keep[%d] = %d out of range", j, keep[j]);
+    a.keep[j] = keep[j];
+    if (out->cols[j].dtype != in->cols[keep[j]].dtype)
+      return set_error(LMS_EINVAL, "output column %d must have the dtype of input column %d", j, keep[j]);
+  }
+  for (int j = 0; j < nproj; ++j)
+    if (out->cols[nkeep + j].dtype != in->cols[projs[j].src].dtype)
+      return set_error(LMS_EINVAL, "output column %d must have the dtype of projection %d's source", nkeep + j, j);
+  for (int j = 0; j < out->ncols; ++j) {
+    if (in->nrows > 0 && !out->cols[j].data) return set_error(LMS_EINVAL, "output column %d is NULL", j);
+    a.out[j] = out->cols[j].data;
+    a.odt[j] = out->cols[j].dtype;
+  }
+  const size_t need = fp_workspace(in->nrows, nullptr, nullptr);
+  if (!workspace || ws_bytes < need)
+    return set_error(LMS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  fp_workspace(in->nrows, &a, workspace);
+  const FpPlan p = fp_plan(in->nrows);
+  a.chunk = p.chunk;
+  a.ntiles = p.ntiles;
+  a.d_count = d_count;
+  hipStream_t st = (hipStream_t)stream;
+  if (in->nrows == 0) {
+    LMS_LAUNCH("k_fp_empty", k_fp_empty, dim3(1), dim3(64), 0, st, a);
+  } else {
+    LMS_LAUNCH("k_fp_count", k_fp_count, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+    LMS_LAUNCH("k_fp_scan", k_fp_scan, dim3(1), dim3(kScanThreads), 0, st, a);
+    LMS_LAUNCH("k_fp_write", k_fp_write, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+  }
+  return check_hip(hipGetLastError(), "filter_project launch");
+}

@@ -1,0 +1,242 @@
+// Internal declarations shared by the HIP sources of liblms (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lms.h"
+
+namespace lms {
+
+constexpr int kMaxCols = 16;
+constexpr int kMaxPreds = 8;
+constexpr int kMaxProjs = 8;
+constexpr int kMaxAggs = 8;
+
+// Kernel-argument image of the row-level part of a query: the columns of a
+// micro-batch, a conjunction of predicates and integer projections.
+struct Query {
+  const void* col[kMaxCols];
+  int32_t dt[kMaxCols];
+  int32_t ncols;
+  int32_t npred;
+  int32_t nproj;
+  int32_t reserved;
+  int32_t pcol[kMaxPreds];
+  int32_t pop[kMaxPreds];
+  int64_t pival[kMaxPreds];
+  double pfval[kMaxPreds];
+  int32_t prsrc[kMaxProjs];
+  int64_t prmul[kMaxProjs];
+  int64_t pradd[kMaxProjs];
+  int64_t nrows;
+};
+
+__device__ __forceinline__ int64_t load_i64(const void* p, int dt, int64_t i) {
+  return dt == LMS_I32 ? (int64_t)((const int32_t*)p)[i] : ((const int64_t*)p)[i];
+}
+
+__device__ __forceinline__ double load_f64(const void* p, int dt, int64_t i) {
+  switch (dt) {
+    case LMS_I32: return (double)((const int32_t*)p)[i];
+    case LMS_I64: return (double)((const int64_t*)p)[i];
+    case LMS_F32: return (double)((const float*)p)[i];
+    default: return ((const double*)p)[i];
+  }
+}
+
+template <class T>
+__device__ __forceinline__ bool compare(T v, int op, T c) {
+  switch (op) {
+    case LMS_LT: return v < c;
+    case LMS_LE: return v <= c;
+    case LMS_GT: return v > c;
+    case LMS_GE: return v >= c;
+    case LMS_EQ: return v == c;
+    default: return v != c;
+  }
+}
+
+__device__ __forceinline__ bool is_int_dtype(int dt) { return dt == LMS_I32 || dt == LMS_I64; }
+
+// Conjunction of the predicates on row i.
+__device__ __forceinline__ bool row_passes(const Query& q, int64_t i) {
+  bool ok = true;
+  for (int k = 0; k < q.npred; ++k) {
+    const int c = q.pcol[k];
+    const int dt = q.dt[c];
+    if (is_int_dtype(dt)) ok = ok && compare<int64_t>(load_i64(q.col[c], dt, i), q.pop[k], q.pival[k]);
+    else ok = ok && compare<double>(load_f64(q.col[c], dt, i), q.pop[k], q.pfval[k]);
+  }
+  return ok;
+}
+
+// Projection j of row i, wrapped to the source column's width.
+__device__ __forceinline__ int64_t project(const Query& q, int j, int64_t i) {
+  const int s = q.prsrc[j];
+  const uint64_t raw = (uint64_t)load_i64(q.col[s], q.dt[s], i) * (uint64_t)q.prmul[j] + (uint64_t)q.pradd[j];
+  return q.dt[s] == LMS_I32 ? (int64_t)(int32_t)(uint32_t)raw : (int64_t)raw;
+}
+
+// Extended columns: input columns followed by projections.
+__device__ __forceinline__ int ext_dtype(const Query& q, int c) {
+  return c < q.ncols ? q.dt[c] : q.dt[q.prsrc[c - q.ncols]];
+}
+__device__ __forceinline__ int64_t ext_i64(const Query& q, int c, int64_t i) {
+  return c < q.ncols ? load_i64(q.col[c], q.dt[c], i) : project(q, c - q.ncols, i);
+}
+__device__ __forceinline__ double ext_f64(const Query& q, int c, int64_t i) {
+  return c < q.ncols ? load_f64(q.col[c], q.dt[c], i) : (double)project(q, c - q.ncols, i);
+}
+
+// MurmurHash3 64-bit finaliser (Appleby), a bijective avalanche mixer.
+__host__ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__host__ __device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+  int64_t q = a / b;
+  if ((a % b) != 0 && a < 0) q -= 1;
+  return q;
+}
+
+// ---- block-wide helpers (blockDim.x = TPB, a multiple of 64) --------------
+
+// Exclusive prefix sum of `v` over the block; `scratch` holds >= TPB/64 + 1
+// words of LDS.  Returns the exclusive prefix; *total receives the block sum.
+template <int TPB>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* scratch, uint32_t* total) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint32_t x = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) scratch[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int w = 0; w < TPB / 64; ++w) {
+      uint32_t t = scratch[w];
+      scratch[w] = run;
+      run += t;
+    }
+    scratch[TPB / 64] = run;
+  }
+  __syncthreads();
+  uint32_t res = scratch[wave] + x - v;
+  *total = scratch[TPB / 64];
+  __syncthreads();
+  return res;
+}
+
+template <int TPB>
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t* scratch) {
+  uint32_t total;
+  block_excl_scan<TPB>(v, scratch, &total);
+  return total;
+}
+
+// In-place exclusive scan of arr[0..n) in LDS; returns the total.
+template <int TPB>
+__device__ __forceinline__ uint32_t block_scan_array(uint32_t* arr, int n, uint32_t* scratch) {
+  const int per = (n + TPB - 1) / TPB;
+  const int lo = threadIdx.x * per;
+  const int hi = min(n, lo + per);
+  uint32_t s = 0;
+  for (int i = lo; i < hi; ++i) s += arr[i];
+  uint32_t total;
+  uint32_t run = block_excl_scan<TPB>(s, scratch, &total);
+  for (int i = lo; i < hi; ++i) {
+    uint32_t t = arr[i];
+    arr[i] = run;
+    run += t;
+  }
+  __syncthreads();
+  return total;
+}
+
+// Single-workgroup exclusive scan of n int64 tile counts (TPB threads, each
+// scanning a contiguous run); writes off[0..n) and *total.
+template <int TPB>
+__device__ void tile_offsets(const int64_t* cnt, int64_t* off, int n, int64_t* total) {
+  __shared__ int64_t sums[TPB];
+  const int per = (n + TPB - 1) / TPB;
+  const int lo = threadIdx.x * per;
+  const int hi = min(n, lo + per);
+  int64_t s = 0;
+  for (int i = lo; i < hi; ++i) s += cnt[i];
+  sums[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int t = 0; t < TPB; ++t) {
+      const int64_t v = sums[t];
+      sums[t] = run;
+      run += v;
+    }
+    *total = run;
+  }
+  __syncthreads();
+  int64_t run = sums[threadIdx.x];
+  for (int i = lo; i < hi; ++i) {
+    const int64_t v = cnt[i];
+    off[i] = run;
+    run += v;
+  }
+}
+
+// Records a device-side status (negative LMS_E* code) in d_count[1].
+__device__ __forceinline__ void set_device_status(int64_t* d_count, int code) {
+  atomicMin((long long*)&d_count[1], (long long)code);
+}
+
+// ---- host side -------------------------------------------------------------
+
+int set_error(int code, const char* fmt, ...);
+
+// Kernel tracing: while lms_trace_enable(1) is in effect, a TraceScope records
+// a hipEvent on `st` when it is created and another when it is destroyed.
+struct TraceScope {
+  int slot = -1;
+  hipStream_t st;
+  TraceScope(const char* name, hipStream_t s);
+  ~TraceScope();
+};
+
+#define LMS_LAUNCH(name, kern, grid, block, lds, st, ...)         \
+  do {                                                             \
+    ::lms::TraceScope lms_trace_scope_(name, st);                  \
+    hipLaunchKernelGGL(kern, grid, block, lds, st, __VA_ARGS__);   \
+  } while (0)
+int check_hip(hipError_t e, const char* what);
+
+// Validates and packs the row-level query; returns LMS_OK or an error code.
+int build_query(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs, int32_t nproj,
+                Query* q);
+
+__host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace (256-byte aligned slices).
+struct WsCarver {
+  char* base;
+  size_t off = 0;
+  explicit WsCarver(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t size() const { return align_up(off, 256); }
+};
+
+}  // namespace lms

@@ -1,0 +1,322 @@
+// Stream-static hash join (Table II "Join (Hash)"; the stream join of LR1,
+// Table III): inner equi-join of a micro-batch against a static table.
+//
+// Build: open addressing with linear probing in a power-of-two table of
+// 16-byte slots (key, payload, used) at load factor <= 0.5; a slot is claimed
+// with one 32-bit CAS, duplicate keys take separate slots.  All slots of a key
+// lie in the run of used slots that starts at its home slot, so a probe walks
+// from the home slot to the first unused slot.
+// Probe: per-tile match counts, a scan of the tile counts, then a write pass
+// that ranks each round of rows with a block prefix, so the pairs come out
+// grouped by ascending probe row without global atomics.
+#include <algorithm>
+
+#include "lms_internal.h"
+
+struct JSlot {
+  int64_t key;
+  int32_t pay;
+  uint32_t used;
+};
+
+struct lms_join_table {
+  JSlot* slots;
+  uint64_t mask;
+  int64_t nbuild;
+  int64_t* d_mult;
+  hipEvent_t built;
+  int64_t mult_cache;
+};
+
+namespace lms {
+namespace {
+
+constexpr int kTPB = 256;
+constexpr int kScanThreads = 1024;
+
+__global__ void k_jb_clear(JSlot* slots, uint64_t nslots, int64_t* d_mult) {
+  const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i < nslots) {
+    slots[i].key = 0;
+    slots[i].pay = 0;
+    slots[i].used = 0;
+  }
+  if (i == 0) *d_mult = 0;
+}
+
+__global__ void k_jb_insert(JSlot* slots, uint64_t mask, const void* keys, int kdt, const int32_t* pay, int64_t n) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t k = load_i64(keys, kdt, j);
+  uint64_t s = fmix64((uint64_t)k) & mask;
+  for (uint64_t t = 0; t <= mask; ++t) {
+    if (atomicCAS(&slots[s].used, 0u, 1u) == 0u) {
+      slots[s].key = k;
+      slots[s].pay = pay[j];
+      return;
+    }
+    s = (s + 1) & mask;
+  }
+}
+
+// Largest number of slots sharing one key.
+__global__ __launch_bounds__(kTPB) void k_jb_mult(const JSlot* slots, uint64_t mask, int64_t* d_mult) {
+  __shared__ uint32_t scratch[kTPB / 64 + 1];
+  __shared__ uint32_t bmax;
+  if (threadIdx.x == 0) bmax = 0;
+  __syncthreads();
+  const uint64_t i = blockIdx.x * (uint64_t)kTPB + threadIdx.x;
+  uint32_t m = 0;
+  if (i <= mask && slots[i].used) {
+    const int64_t k = slots[i].key;
+    uint64_t s = fmix64((uint64_t)k) & mask;
+    for (uint64_t t = 0; t <= mask && slots[s].used; ++t) {
+      m += slots[s].key == k;
+      s = (s + 1) & mask;
+    }
+  }
+  atomicMax(&bmax, m);
+  __syncthreads();
+  if (threadIdx.x == 0 && bmax > 0) atomicMax((unsigned long long*)d_mult, (unsigned long long)bmax);
+  (void)scratch;
+}
+
+struct ProbeArgs {
+  const JSlot* slots;
+  uint64_t mask;
+  const void* pkey;
+  int32_t kdt;
+  int64_t n;
+  int64_t chunk;
+  int32_t ntiles;
+  int64_t* tile_cnt;
+  int64_t* tile_off;
+  uint32_t* out_idx;
+  int32_t* out_pay;
+  int64_t cap;
+  int64_t* d_count;
+};
+
+__device__ __forceinline__ uint32_t count_matches(const ProbeArgs& a, int64_t k) {
+  uint64_t s = fmix64((uint64_t)k) & a.mask;
+  uint32_t c = 0;
+  for (uint64_t t = 0; t <= a.mask; ++t) {
+    const JSlot sl = a.slots[s];
+    if (!sl.used) break;
+    c += sl.key == k;
+    s = (s + 1) & a.mask;
+  }
+  return c;
+}
+
+__global__ __launch_bounds__(kTPB) void k_jp_count(ProbeArgs a) {
+  __shared__ uint32_t scratch[kTPB / 64 + 1];
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = min(a.n, lo + a.chunk);
+  uint32_t c = 0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += kTPB) c += count_matches(a, load_i64(a.pkey, a.kdt, i));
+  c = block_sum<kTPB>(c, scratch);
+  if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_jp_scan(ProbeArgs a) {
+  __shared__ int64_t total;
+  tile_offsets<kScanThreads>(a.tile_cnt, a.tile_off, a.ntiles, &total);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.d_count[0] = total;
+    a.d_count[1] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
+  __shared__ uint32_t scratch[kTPB / 64 + 1];
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = min(a.n, lo + a.chunk);
+  int64_t run = a.tile_off[blockIdx.x];
+  for (int64_t b = lo; b < hi; b += kTPB) {
+    const int64_t i = b + threadIdx.x;
+    int64_t k = 0;
+    uint32_t c = 0;
+    if (i < hi) {
+      k = load_i64(a.pkey, a.kdt, i);
+      c = count_matches(a, k);
+    }
+    uint32_t tot;
+    const uint32_t r = block_excl_scan<kTPB>(c, scratch, &tot);
+    if (c) {
+      int64_t o = run + r;
+      uint64_t s = fmix64((uint64_t)k) & a.mask;
+      for (uint64_t t = 0; t <= a.mask; ++t) {
+        const JSlot sl = a.slots[s];
+        if (!sl.used) break;
+        if (sl.key == k) {
+          if (o < a.cap) {
+            a.out_idx[o] = (uint32_t)i;
+            a.out_pay[o] = sl.pay;
+          }
+          ++o;
+        }
+        s = (s + 1) & a.mask;
+      }
+    }
+    run += tot;
+  }
+}
+
+__global__ void k_jp_empty(int64_t* d_count) {
+  if (threadIdx.x == 0) {
+    d_count[0] = 0;
+    d_count[1] = 0;
+  }
+}
+
+struct JpPlan {
+  int64_t chunk;
+  int ntiles;
+};
+
+JpPlan jp_plan(int64_t n) {
+  JpPlan p;
+  p.chunk = 4096;
+  while ((n + p.chunk - 1) / p.chunk > 65536) p.chunk *= 2;
+  p.ntiles = (int)((n + p.chunk - 1) / p.chunk);
+  return p;
+}
+
+size_t jp_workspace(int64_t n, ProbeArgs* a, void* base) {
+  const JpPlan p = jp_plan(n);
+  WsCarver c(base);
+  int64_t* cnt = c.take<int64_t>(std::max(1, p.ntiles));
+  int64_t* off = c.take<int64_t>(std::max(1, p.ntiles));
+  if (a) {
+    a->tile_cnt = cnt;
+    a->tile_off = off;
+  }
+  return c.size();
+}
+
+}  // namespace
+}  // namespace lms
+
+using namespace lms;
+
+extern "C" int lms_join_build(const lms_batch* tbl, int32_t key_col, int32_t payload_col, lms_join_table** out,
+                              lms_stream stream) {
+  if (!tbl || !out) return set_error(LMS_EINVAL, "table/out is NULL");
+  *out = nullptr;
+  if (tbl->ncols <= 0 || !tbl->cols) return set_error(LMS_EINVAL, "table has no columns");
+  if (key_col < 0 || key_col >= tbl->ncols) return set_error(LMS_EINVAL, "key column %d out of range", key_col);
+  if (payload_col < 0 || payload_col >= tbl->ncols)
+    return set_error(LMS_EINVAL, "payload column %d out of range", payload_col);
+  const int kdt = tbl->cols[key_col].dtype;
+  if (kdt != LMS_I32 && kdt != LMS_I64) return set_error(LMS_EINVAL, "join key must be integer");
+  if (tbl->cols[payload_col].dtype != LMS_I32) return set_error(LMS_EINVAL, "payload column must be int32");
+  if (tbl->nrows < 0 || tbl->nrows >= (int64_t(1) << 31)) return set_error(LMS_EINVAL, "build side must have < 2^31 rows");
+  if (tbl->nrows > 0 && (!tbl->cols[key_col].data || !tbl->cols[payload_col].data))
+    return set_error(LMS_EINVAL, "table column data is NULL");
+  uint64_t nslots = 64;
+  while (nslots < 2 * (uint64_t)tbl->nrows) nslots <<= 1;
+  lms_join_table* t = new lms_join_table{};
+  t->mask = nslots - 1;
+  t->nbuild = tbl->nrows;
+  t->mult_cache = -1;
+  int rc = check_hip(hipMalloc(&t->slots, nslots * sizeof(JSlot)), "hipMalloc join table");
+  if (!rc) rc = check_hip(hipMalloc(&t->d_mult, sizeof(int64_t)), "hipMalloc join counter");
+  if (!rc) rc = check_hip(hipEventCreateWithFlags(&t->built, hipEventDisableTiming), "hipEventCreate");
+  if (rc) {
+    if (t->slots) hipFree(t->slots);
+    if (t->d_mult) hipFree(t->d_mult);
+    delete t;
+    return rc == LMS_EHIP ? LMS_ENOMEM : rc;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  LMS_LAUNCH("k_jb_clear", k_jb_clear, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, st, t->slots, nslots,
+                     t->d_mult);
+  if (tbl->nrows > 0) {
+    LMS_LAUNCH("k_jb_insert", k_jb_insert, dim3((unsigned)((tbl->nrows + 255) / 256)), dim3(256), 0, st, t->slots, t->mask,
+                       (const void*)tbl->cols[key_col].data, kdt, (const int32_t*)tbl->cols[payload_col].data,
+                       tbl->nrows);
+    LMS_LAUNCH("k_jb_mult", k_jb_mult, dim3((unsigned)((nslots + kTPB - 1) / kTPB)), dim3(kTPB), 0, st, t->slots, t->mask,
+                       t->d_mult);
+  }
+  rc = check_hip(hipGetLastError(), "join build launch");
+  if (!rc) rc = check_hip(hipEventRecord(t->built, st), "hipEventRecord");
+  if (rc) {
+    lms_join_free(t);
+    return rc;
+  }
+  *out = t;
+  return LMS_OK;
+}
+
+extern "C" int64_t lms_join_max_mult(lms_join_table* t) {
+  if (!t) return set_error(LMS_EINVAL, "table is NULL");
+  if (t->mult_cache >= 0) return t->mult_cache;
+  int rc = check_hip(hipEventSynchronize(t->built), "hipEventSynchronize");
+  if (rc) return rc;
+  int64_t m = 0;
+  rc = check_hip(hipMemcpy(&m, t->d_mult, sizeof m, hipMemcpyDeviceToHost), "hipMemcpy");
+  if (rc) return rc;
+  t->mult_cache = m;
+  return m;
+}
+
+extern "C" int64_t lms_join_build_rows(const lms_join_table* t) { return t ? t->nbuild : LMS_EINVAL; }
+
+extern "C" void lms_join_free(lms_join_table* t) {
+  if (!t) return;
+  hipEventSynchronize(t->built);
+  hipFree(t->slots);
+  hipFree(t->d_mult);
+  hipEventDestroy(t->built);
+  delete t;
+}
+
+extern "C" size_t lms_hash_join_workspace(int64_t nprobe) {
+  return nprobe < 0 ? 0 : jp_workspace(nprobe, nullptr, nullptr);
+}
+
+extern "C" int lms_hash_join(const lms_join_table* t, const lms_batch* probe, int32_t key_col, uint32_t* out_probe_idx,
+                             int32_t* out_payload, int64_t cap, int64_t* d_count, void* workspace, size_t ws_bytes,
+                             lms_stream stream) {
+  if (!t || !probe || !d_count) return set_error(LMS_EINVAL, "table/probe/d_count is NULL");
+  if (probe->nrows < 0 || probe->nrows >= (int64_t(1) << 32))
+    return set_error(LMS_EINVAL, "probe batch must have < 2^32 rows");
+  if (key_col < 0 || key_col >= probe->ncols || !probe->cols)
+    return set_error(LMS_EINVAL, "probe key column %d out of range", key_col);
+  const int kdt = probe->cols[key_col].dtype;
+  if (kdt != LMS_I32 && kdt != LMS_I64) return set_error(LMS_EINVAL, "probe key must be integer");
+  if (probe->nrows > 0 && !probe->cols[key_col].data) return set_error(LMS_EINVAL, "probe key data is NULL");
+  if (cap < 0) return set_error(LMS_EINVAL, "negative capacity");
+  if (cap > 0 && (!out_probe_idx || !out_payload)) return set_error(LMS_EINVAL, "output arrays are NULL");
+  const size_t need = jp_workspace(probe->nrows, nullptr, nullptr);
+  if (!workspace || ws_bytes < need)
+    return set_error(LMS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  ProbeArgs a{};
+  jp_workspace(probe->nrows, &a, workspace);
+  const JpPlan p = jp_plan(probe->nrows);
+  a.slots = t->slots;
+  a.mask = t->mask;
+  a.pkey = probe->cols[key_col].data;
+  a.kdt = kdt;
+  a.n = probe->nrows;
+  a.chunk = p.chunk;
+  a.ntiles = p.ntiles;
+  a.out_idx = out_probe_idx;
+  a.out_pay = out_payload;
+  a.cap = cap;
+  a.d_count = d_count;
+  hipStream_t st = (hipStream_t)stream;
+  // the build may run on another stream: order this probe after it
+  int rc = check_hip(hipStreamWaitEvent(st, t->built, 0), "hipStreamWaitEvent");
+  if (rc) return rc;
+  if (probe->nrows == 0) {
+    LMS_LAUNCH("k_jp_empty", k_jp_empty, dim3(1), dim3(64), 0, st, d_count);
+  } else {
+    LMS_LAUNCH("k_jp_count", k_jp_count, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+    LMS_LAUNCH("k_jp_scan", k_jp_scan, dim3(1), dim3(kScanThreads), 0, st, a);
+    LMS_LAUNCH("k_jp_write", k_jp_write, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+  }
+  return check_hip(hipGetLastError(), "hash_join launch");
+}

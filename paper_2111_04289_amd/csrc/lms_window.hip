@@ -1,0 +1,1080 @@
+// Windowed hash group-by over tumbling and sliding event-time windows.
+//
+// Semantics: Table II "Aggregation (Hash)" (with "Expand" for sliding
+// windows) under the window model of Table I (SlideTime; 0 = tumbling) and the
+// range/slide clauses of Table III.  A row belongs to every window
+// [origin + k*slide, origin + k*slide + len) that contains its event time.
+//
+// Method (MI355X-first; the paper delegates these operators to Spark-Rapids):
+//  * Pane decomposition replaces Expand: with pane = gcd(len, slide) every
+//    window is the union of len/pane consecutive panes, and each row falls in
+//    exactly one pane, so the row scan does one insertion per row instead of
+//    len/slide.
+//  * Device-scope global atomics on gfx950 run at the memory side (tens of
+//    G ops/s for the whole chip), so no per-row global atomic is used.  Rows are
+//    radix-partitioned by a hash of the key (hist -> scan -> scatter) so that
+//    all panes of a key land in one partition, and each partition is
+//    aggregated in a workgroup's LDS hash tables, where the sliding windows are
+//    also composed from the key's panes and emitted.
+//  * Zipf-hot partitions are cut into row pieces aggregated by separate
+//    workgroups whose LDS partial tables are flushed as partial records and
+//    merged by a second launch.
+//  * A partition whose groups exceed the LDS tables is re-aggregated in
+//    sub-ranges of a second key hash (halving until it fits).
+#include <algorithm>
+#include <cstring>
+
+#include "lms_internal.h"
+
+namespace lms {
+namespace {
+
+constexpr int kScanTPB = 256;
+constexpr int kAggTPB = 512;
+constexpr uint64_t kEmptyKey = 0x8000000000000000ull;
+constexpr uint64_t kEmptyGid = ~0ull;
+constexpr int kLdsLimit = 160 * 1024;
+constexpr int kStackCap = 80;
+constexpr int kUnroll = 4;
+
+struct Item {
+  uint32_t p, lo, hi, first;
+  uint32_t kp, reserved[3];
+};
+
+struct PartInfo {
+  uint32_t first, kp;
+};
+
+struct WinArgs {
+  Query q;
+  int32_t key_col, ts_col;
+  int64_t len, slide, origin, pane, R, W;
+  double inv_pane;
+  double inv_R;
+  int32_t nagg;
+  int32_t afn[kMaxAggs];
+  int32_t aacc[kMaxAggs];  // accumulator slot of aggregate a (-1 for COUNT)
+  int32_t nval;
+  int32_t vcol[kMaxAggs];  // extended column staged as value column v
+  int32_t vdt[kMaxAggs];   // dtype of staged value column v
+  int32_t nacc;
+  int32_t accfn[kMaxAggs];   // aggregate function of accumulator slot s
+  int32_t accval[kMaxAggs];  // staged value column feeding slot s
+  int32_t pbits, nparts, g1, max_items, ek, eg;
+  int64_t chunk, rs;
+  // workspace
+  int64_t* hdr;  // [0] base pane B0, [1] number of items
+  uint32_t* H;
+  uint32_t* Off;
+  uint32_t* Rp;
+  PartInfo* pinfo;
+  Item* items;
+  uint32_t* pcount;
+  int64_t* skey;
+  uint32_t* spane;
+  void* sval[kMaxAggs];
+  int64_t* pkey;
+  uint32_t* ppane;
+  uint32_t* pcnt;
+  uint64_t* pacc[kMaxAggs];
+  // outputs
+  int64_t* okey;
+  int64_t* ows;
+  void* oagg[kMaxAggs];
+  int64_t cap;
+  int64_t* d_count;
+};
+
+__device__ __forceinline__ int part_of(uint64_t h, int pbits) { return pbits ? (int)(h >> (64 - pbits)) : 0; }
+__device__ __forceinline__ uint32_t subhash(uint64_t h) { return (uint32_t)(h >> 16); }
+
+// Quotient of rel >= 0 by pane, exact: double estimate then integer fix-up.
+__device__ __forceinline__ uint64_t div_pane(uint64_t rel, int64_t pane, double inv) {
+  if (rel < (1ull << 52)) {
+    uint64_t q = (uint64_t)((double)rel * inv);
+    int64_t r = (int64_t)(rel - q * (uint64_t)pane);
+    while (r < 0) {
+      --q;
+      r += pane;
+    }
+    while (r >= pane) {
+      ++q;
+      r -= pane;
+    }
+    return q;
+  }
+  return rel / (uint64_t)pane;
+}
+
+// ---- kernels 1-4: partition rows by key hash --------------------------------
+
+__global__ void k_wa_init(WinArgs a) {
+  if (threadIdx.x == 0) {
+    a.d_count[0] = 0;
+    a.d_count[1] = 0;
+    a.hdr[1] = 0;
+    int64_t b0 = 0;
+    if (a.q.nrows > 0) {
+      const int64_t ts0 = load_i64(a.q.col[a.ts_col], a.q.dt[a.ts_col], 0);
+      const int64_t q0 = floor_div(ts0 - a.origin, a.pane);
+      b0 = a.R * floor_div(q0 - (int64_t(1) << 31), a.R);
+    }
+    a.hdr[0] = b0;
+  }
+}
+
+__global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
+  extern __shared__ uint32_t hist[];
+  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) hist[p] = 0;
+  __syncthreads();
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = min(a.q.nrows, lo + a.chunk);
+  const void* kc = a.q.col[a.key_col];
+  const int kdt = a.q.dt[a.key_col];
+  // kUnroll rows per thread per step: all loads are issued before any use
+  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kUnroll) {
+    bool ok[kUnroll];
+    int64_t key[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = b + (int64_t)u * kScanTPB;
+      ok[u] = i < hi && row_passes(a.q, i);
+      key[u] = i < hi ? load_i64(kc, kdt, i) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (ok[u]) atomicAdd(&hist[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) a.H[(size_t)p * a.g1 + blockIdx.x] = hist[p];
+}
+
+// Rows per partition.
+__global__ __launch_bounds__(kScanTPB) void k_wa_scan1(WinArgs a) {
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  const int p = blockIdx.x;
+  uint32_t s = 0;
+  for (int w = threadIdx.x; w < a.g1; w += kScanTPB) s += a.H[(size_t)p * a.g1 + w];
+  s = block_sum<kScanTPB>(s, scratch);
+  if (threadIdx.x == 0) a.Rp[p] = s;
+}
+
+// Partition starts, per-(partition, chunk) write offsets and the work items of
+// the aggregation (a partition of R rows gives ceil(R / rs) items).
+__global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  const int p = blockIdx.x;
+  uint32_t s_rows = 0, s_items = 0;
+  for (int q = threadIdx.x; q < p; q += kScanTPB) {
+    const uint32_t r = a.Rp[q];
+    s_rows += r;
+    s_items += (uint32_t)((r + a.rs - 1) / a.rs);
+  }
+  const uint32_t start = block_sum<kScanTPB>(s_rows, scratch);
+  const uint32_t ibase = block_sum<kScanTPB>(s_items, scratch);
+  const uint32_t rp = a.Rp[p];
+  const uint32_t kp = (uint32_t)((rp + a.rs - 1) / a.rs);
+  // exclusive scan of H[p][*] over the chunks
+  const int per = (a.g1 + kScanTPB - 1) / kScanTPB;
+  const int w0 = threadIdx.x * per;
+  const int w1 = min(a.g1, w0 + per);
+  uint32_t loc = 0;
+  for (int w = w0; w < w1; ++w) loc += a.H[(size_t)p * a.g1 + w];
+  uint32_t total;
+  uint32_t run = start + block_excl_scan<kScanTPB>(loc, scratch, &total);
+  for (int w = w0; w < w1; ++w) {
+    const uint32_t c = a.H[(size_t)p * a.g1 + w];
+    a.Off[(size_t)p * a.g1 + w] = run;
+    run += c;
+  }
+  for (uint32_t j = threadIdx.x; j < kp; j += kScanTPB) {
+    Item it;
+    it.p = p;
+    it.lo = start + (uint32_t)(j * a.rs);
+    it.hi = (uint32_t)min((int64_t)start + rp, (int64_t)it.lo + a.rs);
+    it.first = ibase;
+    it.kp = kp;
+    it.reserved[0] = it.reserved[1] = it.reserved[2] = 0;
+    a.items[ibase + j] = it;
+  }
+  if (threadIdx.x == 0) {
+    a.pinfo[p].first = ibase;
+    a.pinfo[p].kp = kp;
+    if (p == a.nparts - 1) a.hdr[1] = ibase + kp;
+  }
+}
+
+// Scatter the passing rows, as (key, pane, value columns), to their partition.
+__global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
+  extern __shared__ uint32_t cursor[];
+  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) cursor[p] = a.Off[(size_t)p * a.g1 + blockIdx.x];
+  __syncthreads();
+  const int64_t b0 = a.hdr[0];
+  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t hi = min(a.q.nrows, lo + a.chunk);
+  const void* kc = a.q.col[a.key_col];
+  const int kdt = a.q.dt[a.key_col];
+  const void* tc = a.q.col[a.ts_col];
+  const int tdt = a.q.dt[a.ts_col];
+  bool range_err = false;
+  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kUnroll) {
+    bool ok[kUnroll];
+    int64_t key[kUnroll], ts[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t i = b + (int64_t)u * kScanTPB;
+      ok[u] = i < hi && row_passes(a.q, i);
+      key[u] = i < hi ? load_i64(kc, kdt, i) : 0;
+      ts[u] = i < hi ? load_i64(tc, tdt, i) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (!ok[u]) continue;
+      const int64_t i = b + (int64_t)u * kScanTPB;
+      const uint32_t pos = atomicAdd(&cursor[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
+      const int64_t rel = ts[u] - a.origin - b0 * a.pane;
+      uint64_t qp = 0;
+      if (rel < 0) range_err = true;
+      else qp = div_pane((uint64_t)rel, a.pane, a.inv_pane);
+      if (qp >= (1ull << 32)) {
+        range_err = true;
+        qp = 0;
+      }
+      a.skey[pos] = key[u];
+      a.spane[pos] = (uint32_t)qp;
+#pragma unroll
+      for (int v = 0; v < kMaxAggs; ++v) {
+        if (v < a.nval) {
+          const int c = a.vcol[v];
+          switch (a.vdt[v]) {
+            case LMS_I32: ((int32_t*)a.sval[v])[pos] = (int32_t)ext_i64(a.q, c, i); break;
+            case LMS_I64: ((int64_t*)a.sval[v])[pos] = ext_i64(a.q, c, i); break;
+            case LMS_F32: ((float*)a.sval[v])[pos] = ((const float*)a.q.col[c])[i]; break;
+            default: ((double*)a.sval[v])[pos] = ((const double*)a.q.col[c])[i]; break;
+          }
+        }
+      }
+    }
+  }
+  if (range_err) set_device_status(a.d_count, LMS_ERANGE);
+}
+
+// LDS layout of one aggregation workgroup.
+struct Lds {
+  uint64_t* keys;  // ek + 1 (slot ek holds the key equal to the empty marker)
+  uint32_t* kcnt;  // ek + 1: groups per key
+  uint32_t* kaux;  // ek + 1: start of the key's run in `order`
+  uint32_t* nwin;  // ek + 1: fill counter, then windows per key, then output offsets
+  uint64_t* gid;   // eg: (key slot << 32) | pane, or kEmptyGid
+  uint64_t* acc;   // nacc * eg: accumulator k of group g at acc[k * eg + g]
+  uint32_t* gcnt;  // eg: rows per group
+  uint32_t* order; // eg: group slots ordered by key
+  uint32_t* scan;  // kAggTPB / 64 + 1
+  uint32_t* misc;  // flags and broadcasts
+  uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
+};
+
+enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_WORDS = 16 };
+
+__host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
+  size_t b = 0;
+  b += align_up((size_t)(ek + 1) * 8, 16);
+  b += 3 * align_up((size_t)(ek + 1) * 4, 16);
+  b += (size_t)eg * 8 + (size_t)nacc * eg * 8 + (size_t)eg * 4 + (size_t)eg * 4;
+  b += align_up((kAggTPB / 64 + 1) * 4, 16) + M_WORDS * 4;
+  b += 2 * kStackCap * 8;
+  return b;
+}
+
+__device__ __forceinline__ Lds carve_lds(char* base, int ek, int eg, int nacc) {
+  Lds s;
+  size_t o = 0;
+  s.keys = (uint64_t*)(base + o);
+  o += align_up((size_t)(ek + 1) * 8, 16);
+  s.kcnt = (uint32_t*)(base + o);
+  o += align_up((size_t)(ek + 1) * 4, 16);
+  s.kaux = (uint32_t*)(base + o);
+  o += align_up((size_t)(ek + 1) * 4, 16);
+  s.nwin = (uint32_t*)(base + o);
+  o += align_up((size_t)(ek + 1) * 4, 16);
+  s.gid = (uint64_t*)(base + o);
+  o += (size_t)eg * 8;
+  s.acc = (uint64_t*)(base + o);
+  o += (size_t)nacc * eg * 8;
+  s.gcnt = (uint32_t*)(base + o);
+  o += (size_t)eg * 4;
+  s.order = (uint32_t*)(base + o);
+  o += (size_t)eg * 4;
+  s.scan = (uint32_t*)(base + o);
+  o += align_up((kAggTPB / 64 + 1) * 4, 16);
+  s.misc = (uint32_t*)(base + o);
+  o += M_WORDS * 4;
+  s.stack = (uint64_t*)(base + o);
+  return s;
+}
+
+__device__ __forceinline__ uint64_t acc_identity(int fn) {
+  if (fn == LMS_MIN) return (uint64_t)INT64_MAX;
+  if (fn == LMS_MAX) return (uint64_t)INT64_MIN;
+  return 0;  // SUM: 0; AVG: +0.0
+}
+
+__device__ __forceinline__ uint64_t combine(int fn, uint64_t x, uint64_t y) {
+  switch (fn) {
+    case LMS_SUM: return x + y;
+    case LMS_MIN: return (int64_t)y < (int64_t)x ? y : x;
+    case LMS_MAX: return (int64_t)y > (int64_t)x ? y : x;
+    default:
+      return (uint64_t)__double_as_longlong(__longlong_as_double((long long)x) + __longlong_as_double((long long)y));
+  }
+}
+
+__device__ void clear_tables(const WinArgs& a, Lds& s) {
+  for (int i = threadIdx.x; i <= a.ek; i += kAggTPB) {
+    s.keys[i] = kEmptyKey;
+    s.kcnt[i] = 0;
+    s.kaux[i] = 0;
+    s.nwin[i] = 0;
+  }
+  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
+    s.gid[g] = kEmptyGid;
+    s.gcnt[g] = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxAggs; ++k) {
+    if (k < a.nacc) {
+      const uint64_t id = acc_identity(a.accfn[k]);
+      for (int g = threadIdx.x; g < a.eg; g += kAggTPB) s.acc[(size_t)k * a.eg + g] = id;
+    }
+  }
+}
+
+// One input element: a staged row (cnt 1) or a partial record.  Only ever
+// indexed with compile-time indices, so it lives in registers.
+struct Elem {
+  int64_t key;
+  uint32_t pane;
+  uint32_t cnt;
+  uint64_t in[kMaxAggs];  // input of accumulator k (int64 or double bits)
+};
+
+__device__ __forceinline__ void load_row(const WinArgs& a, uint32_t e, Elem& x) {
+  x.key = a.skey[e];
+  x.pane = a.spane[e];
+  x.cnt = 1;
+  uint64_t raw[kMaxAggs];  // staged value v: int64, or double bits for float columns
+#pragma unroll
+  for (int v = 0; v < kMaxAggs; ++v) {
+    raw[v] = 0;
+    if (v < a.nval) {
+      const void* c = a.sval[v];
+      switch (a.vdt[v]) {
+        case LMS_I32: raw[v] = (uint64_t)(int64_t)((const int32_t*)c)[e]; break;
+        case LMS_I64: raw[v] = ((const uint64_t*)c)[e]; break;
+        case LMS_F32: raw[v] = (uint64_t)__double_as_longlong((double)((const float*)c)[e]); break;
+        default: raw[v] = ((const uint64_t*)c)[e]; break;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kMaxAggs; ++k) {
+    x.in[k] = 0;
+    if (k < a.nacc) {
+      const int v = a.accval[k];
+      uint64_t r = raw[0];
+#pragma unroll
+      for (int j = 1; j < kMaxAggs; ++j) r = v == j ? raw[j] : r;
+      const bool is_int = a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_I64;
+      x.in[k] = (a.accfn[k] == LMS_AVG && is_int) ? (uint64_t)__double_as_longlong((double)(int64_t)r) : r;
+    }
+  }
+}
+
+__device__ __forceinline__ void load_partial(const WinArgs& a, uint32_t e, Elem& x) {
+  x.key = a.pkey[e];
+  x.pane = a.ppane[e];
+  x.cnt = a.pcnt[e];
+#pragma unroll
+  for (int k = 0; k < kMaxAggs; ++k) x.in[k] = k < a.nacc ? a.pacc[k][e] : 0;
+}
+
+__device__ __forceinline__ uint32_t group_hash(uint64_t gid) {
+  uint32_t h = (uint32_t)gid * 0x9E3779B1u + (uint32_t)(gid >> 32) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  return h;
+}
+
+// Inserts one element; returns false if a table is full.
+__device__ __forceinline__ bool insert(const WinArgs& a, Lds& s, const Elem& x, uint64_t h) {
+  int kid;
+  if ((uint64_t)x.key == kEmptyKey) {
+    kid = a.ek;
+    s.keys[a.ek] = kEmptyKey;
+  } else {
+    kid = -1;
+    uint32_t slot = (uint32_t)h & (uint32_t)(a.ek - 1);
+    for (int t = 0; t < a.ek; ++t) {
+      const uint64_t cur = __atomic_load_n(&s.keys[slot], __ATOMIC_RELAXED);
+      if (cur == (uint64_t)x.key) {
+        kid = (int)slot;
+        break;
+      }
+      if (cur == kEmptyKey) {
+        const uint64_t old = atomicCAS((unsigned long long*)&s.keys[slot], (unsigned long long)kEmptyKey,
+                                       (unsigned long long)x.key);
+        if (old == kEmptyKey || old == (uint64_t)x.key) {
+          kid = (int)slot;
+          break;
+        }
+      }
+      slot = (slot + 1) & (uint32_t)(a.ek - 1);
+    }
+    if (kid < 0) return false;
+  }
+  const uint64_t gid = ((uint64_t)kid << 32) | x.pane;
+  int g = -1;
+  uint32_t slot = group_hash(gid) & (uint32_t)(a.eg - 1);
+  for (int t = 0; t < a.eg; ++t) {
+    const uint64_t cur = __atomic_load_n(&s.gid[slot], __ATOMIC_RELAXED);
+    if (cur == gid) {
+      g = (int)slot;
+      break;
+    }
+    if (cur == kEmptyGid) {
+      const uint64_t old = atomicCAS((unsigned long long*)&s.gid[slot], (unsigned long long)kEmptyGid,
+                                     (unsigned long long)gid);
+      if (old == kEmptyGid || old == gid) {
+        g = (int)slot;
+        break;
+      }
+    }
+    slot = (slot + 1) & (uint32_t)(a.eg - 1);
+  }
+  if (g < 0) return false;
+  atomicAdd(&s.gcnt[g], x.cnt);
+#pragma unroll
+  for (int k = 0; k < kMaxAggs; ++k) {
+    if (k < a.nacc) {
+      uint64_t* p = s.acc + (size_t)k * a.eg + g;
+      switch (a.accfn[k]) {
+        case LMS_SUM: atomicAdd((unsigned long long*)p, (unsigned long long)x.in[k]); break;
+        case LMS_MIN: atomicMin((long long*)p, (long long)x.in[k]); break;
+        case LMS_MAX: atomicMax((long long*)p, (long long)x.in[k]); break;
+        default: unsafeAtomicAdd((double*)p, __longlong_as_double((long long)x.in[k])); break;
+      }
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ int64_t key_of(const WinArgs& a, const Lds& s, uint32_t kid) {
+  return kid == (uint32_t)a.ek ? (int64_t)kEmptyKey : (int64_t)s.keys[kid];
+}
+
+// Reserves `total` output rows; returns the first index (broadcast to all).
+__device__ int64_t reserve_output(const WinArgs& a, Lds& s, uint32_t total) {
+  if (threadIdx.x == 0) {
+    const unsigned long long b = atomicAdd((unsigned long long*)&a.d_count[0], (unsigned long long)total);
+    s.misc[M_BASE_LO] = (uint32_t)b;
+    s.misc[M_BASE_HI] = (uint32_t)(b >> 32);
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)(((uint64_t)s.misc[M_BASE_HI] << 32) | s.misc[M_BASE_LO]);
+  __syncthreads();
+  return base;
+}
+
+// Tumbling windows: every group (key, pane) is one output row.
+__device__ void emit_tumbling(const WinArgs& a, Lds& s, int64_t b0) {
+  uint32_t mine = 0;
+  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) mine += s.gid[g] != kEmptyGid;
+  const uint32_t total = block_sum<kAggTPB>(mine, s.scan);
+  if (total == 0) return;
+  const int64_t base = reserve_output(a, s, total);
+  uint32_t run = 0;
+  for (int g0 = 0; g0 < a.eg; g0 += kAggTPB) {
+    const int g = g0 + threadIdx.x;
+    const bool occ = g < a.eg && s.gid[g] != kEmptyGid;
+    uint32_t rtot;
+    const uint32_t r = block_excl_scan<kAggTPB>(occ ? 1u : 0u, s.scan, &rtot);
+    if (occ) {
+      const int64_t idx = base + run + r;
+      if (idx < a.cap) {
+        const uint64_t gid = s.gid[g];
+        const uint32_t cnt = s.gcnt[g];
+        a.okey[idx] = key_of(a, s, (uint32_t)(gid >> 32));
+        a.ows[idx] = a.origin + (b0 + (int64_t)(uint32_t)gid) * a.len;
+#pragma unroll
+        for (int k = 0; k < kMaxAggs; ++k) {
+          if (k < a.nagg) {
+            const int fn = a.afn[k];
+            if (fn == LMS_COUNT) {
+              ((int64_t*)a.oagg[k])[idx] = cnt;
+            } else {
+              const uint64_t v = s.acc[(size_t)a.aacc[k] * a.eg + g];
+              if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)v) / (double)cnt;
+              else ((int64_t*)a.oagg[k])[idx] = (int64_t)v;
+            }
+          }
+        }
+      }
+    }
+    run += rtot;
+  }
+}
+
+// floor(x / d) for d > 0 and |x| < 2^52: a double estimate corrected exactly.
+__device__ __forceinline__ int64_t fdiv(int64_t x, int64_t d, double inv) {
+  int64_t q = (int64_t)floor((double)x * inv);
+  int64_t r = x - q * d;
+  while (r < 0) {
+    --q;
+    r += d;
+  }
+  while (r >= d) {
+    ++q;
+    r -= d;
+  }
+  return q;
+}
+
+// Windows of one key from its pane-sorted groups; calls emit(w, jlo, jhi) for
+// each window w (relative index) that contains the key's panes jlo..jhi.  Pane
+// q lies in windows floor((q - W) / R) + 1 .. floor(q / R).
+template <class F>
+__device__ __forceinline__ uint32_t sweep_windows(const WinArgs& a, const Lds& s, const uint32_t* list, uint32_t m,
+                                                  F emit) {
+  auto pane_at = [&](uint32_t j) { return (int64_t)(uint32_t)s.gid[list[j]]; };
+  auto first_win = [&](int64_t q) { return fdiv(q - a.W, a.R, a.inv_R) + 1; };
+  auto last_win = [&](int64_t q) { return fdiv(q, a.R, a.inv_R); };
+  uint32_t nout = 0, next = 0, jlo = 0;
+  int64_t jhi = -1;
+  int64_t fnext = first_win(pane_at(0));
+  int64_t llo = last_win(pane_at(0));
+  int64_t w = fnext;
+  for (;;) {
+    while (next < m && fnext <= w) {
+      jhi = next;
+      ++next;
+      if (next < m) fnext = first_win(pane_at(next));
+    }
+    while ((int64_t)jlo <= jhi && llo < w) {
+      ++jlo;
+      if (jlo < m) llo = last_win(pane_at(jlo));
+    }
+    if ((int64_t)jlo > jhi) {
+      if (next >= m) break;
+      w = fnext;
+      continue;
+    }
+    emit(w, jlo, (uint32_t)jhi);
+    ++nout;
+    ++w;
+  }
+  return nout;
+}
+
+// Sliding windows: group the (key, pane) entries by key, order each key's
+// panes, then emit every window holding at least one of them.
+__device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
+  const int nk = a.ek + 1;
+  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
+    const uint64_t gid = s.gid[g];
+    if (gid != kEmptyGid) atomicAdd(&s.kcnt[(uint32_t)(gid >> 32)], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nk; i += kAggTPB) s.kaux[i] = s.kcnt[i];
+  __syncthreads();
+  block_scan_array<kAggTPB>(s.kaux, nk, s.scan);
+  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
+    const uint64_t gid = s.gid[g];
+    if (gid != kEmptyGid) {
+      const uint32_t kid = (uint32_t)(gid >> 32);
+      s.order[s.kaux[kid] + atomicAdd(&s.nwin[kid], 1u)] = (uint32_t)g;
+    }
+  }
+  __syncthreads();
+  for (int kid = threadIdx.x; kid < nk; kid += kAggTPB) {
+    const uint32_t m = s.kcnt[kid];
+    if (m == 0) {
+      s.nwin[kid] = 0;
+      continue;
+    }
+    uint32_t* list = s.order + s.kaux[kid];
+    for (uint32_t i = 1; i < m; ++i) {  // insertion sort by pane
+      const uint32_t g = list[i];
+      const uint32_t p = (uint32_t)s.gid[g];
+      int j = (int)i - 1;
+      while (j >= 0 && (uint32_t)s.gid[list[j]] > p) {
+        list[j + 1] = list[j];
+        --j;
+      }
+      list[j + 1] = g;
+    }
+    s.nwin[kid] = sweep_windows(a, s, list, m, [](int64_t, uint32_t, uint32_t) {});
+  }
+  __syncthreads();
+  const uint32_t total = block_scan_array<kAggTPB>(s.nwin, nk, s.scan);
+  if (total == 0) return;
+  const int64_t base = reserve_output(a, s, total);
+  const int64_t wbase = b0 / a.R;
+  for (int kid = threadIdx.x; kid < nk; kid += kAggTPB) {
+    const uint32_t m = s.kcnt[kid];
+    if (m == 0) continue;
+    const uint32_t* list = s.order + s.kaux[kid];
+    const int64_t key = key_of(a, s, (uint32_t)kid);
+    int64_t idx = base + s.nwin[kid];
+    sweep_windows(a, s, list, m, [&](int64_t w, uint32_t jlo, uint32_t jhi) {
+      if (idx < a.cap) {
+        uint32_t cnt = 0;
+        for (uint32_t j = jlo; j <= jhi; ++j) cnt += s.gcnt[list[j]];
+        a.okey[idx] = key;
+        a.ows[idx] = a.origin + (w + wbase) * a.slide;
+#pragma unroll
+        for (int k = 0; k < kMaxAggs; ++k) {
+          if (k < a.nagg) {
+            const int fn = a.afn[k];
+            if (fn == LMS_COUNT) {
+              ((int64_t*)a.oagg[k])[idx] = cnt;
+            } else {
+              const uint64_t* accs = s.acc + (size_t)a.aacc[k] * a.eg;
+              uint64_t v = acc_identity(fn);
+              for (uint32_t j = jlo; j <= jhi; ++j) v = combine(fn, v, accs[list[j]]);
+              if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)v) / (double)cnt;
+              else ((int64_t*)a.oagg[k])[idx] = (int64_t)v;
+            }
+          }
+        }
+      }
+      ++idx;
+    });
+  }
+}
+
+// Segments of input elements: raw staged rows [lo, hi), or the partial records
+// written by the pieces of a split partition.
+struct Segments {
+  bool partial;
+  uint32_t lo, hi;     // raw rows
+  uint32_t first, kp;  // partial: items first .. first+kp-1
+};
+
+__device__ __forceinline__ void seg_range(const WinArgs& a, const Segments& sg, uint32_t j, uint32_t& lo,
+                                          uint32_t& hi) {
+  if (!sg.partial) {
+    lo = sg.lo;
+    hi = sg.hi;
+  } else {
+    lo = a.items[sg.first + j].lo;
+    hi = lo + a.pcount[sg.first + j];
+  }
+}
+
+// Aggregates every element whose key hash lies in sub-ranges of [0, 2^32),
+// starting with the whole range and halving a range whenever its groups do not
+// fit the LDS tables, then composes and emits its windows.
+__device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg) {
+  const int64_t b0 = a.hdr[0];
+  const uint32_t nseg = sg.partial ? sg.kp : 1;
+  if (threadIdx.x == 0) {
+    s.stack[0] = 0;
+    s.stack[1] = 1ull << 32;
+    s.misc[M_SSIZE] = 1;
+  }
+  __syncthreads();
+  while (true) {
+    const uint32_t ssize = s.misc[M_SSIZE];
+    if (ssize == 0) break;
+    const uint64_t rlo = s.stack[2 * (ssize - 1)];
+    const uint64_t rhi = s.stack[2 * (ssize - 1) + 1];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s.misc[M_SSIZE] = ssize - 1;
+      s.misc[M_OVF] = 0;
+    }
+    clear_tables(a, s);
+    __syncthreads();
+    bool ovf = false;
+    for (uint32_t j = 0; j < nseg && !ovf; ++j) {
+      uint32_t lo, hi;
+      seg_range(a, sg, j, lo, hi);
+      for (uint32_t b = lo; b < hi; b += kAggTPB) {
+        const uint32_t e = b + threadIdx.x;
+        if (e < hi) {
+          Elem x;
+          if (sg.partial) load_partial(a, e, x);
+          else load_row(a, e, x);
+          const uint64_t h = fmix64((uint64_t)x.key);
+          const uint32_t sh = subhash(h);
+          if (sh >= rlo && sh < rhi) {
+            if (!insert(a, s, x, h)) s.misc[M_OVF] = 1;
+          }
+        }
+        __syncthreads();
+        const bool o = s.misc[M_OVF] != 0;
+        __syncthreads();  // every thread has read the flag before the next round may set it
+        if (o) {
+          ovf = true;
+          break;
+        }
+      }
+    }
+    __syncthreads();
+    if (ovf) {
+      if (threadIdx.x == 0) {
+        const uint32_t n = s.misc[M_SSIZE];
+        if (rhi - rlo <= 1 || n + 2 > kStackCap) {
+          set_device_status(a.d_count, LMS_ECAPACITY);
+        } else {
+          const uint64_t mid = rlo + (rhi - rlo) / 2;
+          s.stack[2 * n] = rlo;
+          s.stack[2 * n + 1] = mid;
+          s.stack[2 * n + 2] = mid;
+          s.stack[2 * n + 3] = rhi;
+          s.misc[M_SSIZE] = n + 2;
+        }
+      }
+      __syncthreads();
+      continue;
+    }
+    if (a.R == 1 && a.W == 1) emit_tumbling(a, s, b0);
+    else emit_sliding(a, s, b0);
+    __syncthreads();
+  }
+}
+
+// Writes the groups in the LDS tables as partial records at dst + pc.
+__device__ void flush_partials(const WinArgs& a, Lds& s, uint32_t dst) {
+  uint32_t run = s.misc[M_PC];
+  for (int g0 = 0; g0 < a.eg; g0 += kAggTPB) {
+    const int g = g0 + threadIdx.x;
+    const bool occ = g < a.eg && s.gid[g] != kEmptyGid;
+    uint32_t rtot;
+    const uint32_t r = block_excl_scan<kAggTPB>(occ ? 1u : 0u, s.scan, &rtot);
+    if (occ) {
+      const uint32_t e = dst + run + r;
+      const uint64_t gid = s.gid[g];
+      a.pkey[e] = key_of(a, s, (uint32_t)(gid >> 32));
+      a.ppane[e] = (uint32_t)gid;
+      a.pcnt[e] = s.gcnt[g];
+#pragma unroll
+      for (int k = 0; k < kMaxAggs; ++k)
+        if (k < a.nacc) a.pacc[k][e] = s.acc[(size_t)k * a.eg + g];
+    }
+    run += rtot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) s.misc[M_PC] = run;
+  __syncthreads();
+}
+
+// One piece of a split partition: aggregate its rows into partial records.
+// When a table fills up, the tables are flushed and the rows that did not fit
+// are inserted again into the emptied tables (at most one per thread, so they
+// always fit).
+__device__ void aggregate_piece(const WinArgs& a, Lds& s, uint32_t item, const Item& it) {
+  if (threadIdx.x == 0) {
+    s.misc[M_PC] = 0;
+    s.misc[M_OVF] = 0;
+  }
+  clear_tables(a, s);
+  __syncthreads();
+  for (uint32_t b = it.lo; b < it.hi; b += kAggTPB) {
+    const uint32_t e = b + threadIdx.x;
+    bool pending = false;
+    Elem x;
+    uint64_t h = 0;
+    if (e < it.hi) {
+      load_row(a, e, x);
+      h = fmix64((uint64_t)x.key);
+      if (!insert(a, s, x, h)) {
+        pending = true;
+        s.misc[M_OVF] = 1;
+      }
+    }
+    __syncthreads();
+    const bool o = s.misc[M_OVF] != 0;
+    __syncthreads();
+    if (o) {
+      flush_partials(a, s, it.lo);
+      clear_tables(a, s);
+      if (threadIdx.x == 0) s.misc[M_OVF] = 0;
+      __syncthreads();
+      if (pending) insert(a, s, x, h);
+      __syncthreads();
+    }
+  }
+  flush_partials(a, s, it.lo);
+  if (threadIdx.x == 0) a.pcount[item] = s.misc[M_PC];
+}
+
+__global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
+  const uint32_t item = blockIdx.x;
+  if ((int64_t)item >= a.hdr[1]) return;
+  extern __shared__ __align__(16) char lds_raw[];
+  Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
+  const Item it = a.items[item];
+  if (it.kp > 1) {
+    aggregate_piece(a, s, item, it);
+  } else {
+    Segments sg{false, it.lo, it.hi, 0, 0};
+    aggregate_and_emit(a, s, sg);
+  }
+}
+
+__global__ __launch_bounds__(kAggTPB) void k_wa_merge(WinArgs a) {
+  const PartInfo pi = a.pinfo[blockIdx.x];
+  if (pi.kp <= 1) return;
+  extern __shared__ __align__(16) char lds_raw[];
+  Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
+  Segments sg{true, 0, 0, pi.first, pi.kp};
+  aggregate_and_emit(a, s, sg);
+}
+
+// ---- host planning -------------------------------------------------------------
+
+int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+int ilog2(int64_t x) {
+  int b = 0;
+  while ((int64_t(1) << b) < x) ++b;
+  return b;
+}
+
+struct Plan {
+  int64_t n;
+  int64_t chunk;
+  int g1;
+  int nparts, pbits;
+  int64_t rs;
+  int max_items;
+  int ek, eg;
+  size_t lds;
+  int nval, nacc;
+};
+
+int64_t gcd64(int64_t x, int64_t y) {
+  while (y) {
+    int64_t t = x % y;
+    x = y;
+    y = t;
+  }
+  return x;
+}
+
+Plan make_plan(int64_t n, int nval, int nacc) {
+  Plan p{};
+  p.n = n;
+  p.chunk = std::min<int64_t>(65536, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
+  p.g1 = (int)((n + p.chunk - 1) / p.chunk);
+  p.nparts = (int)std::min<int64_t>(4096, std::max<int64_t>(8, next_pow2((n + 16383) / 16384)));
+  p.pbits = ilog2(p.nparts);
+  p.rs = 8192;
+  p.max_items = p.nparts + (int)((n + p.rs - 1) / p.rs);
+  p.eg = 2048;
+  p.ek = 1024;
+  while (lds_bytes(p.ek, p.eg, nacc) > (size_t)kLdsLimit && p.eg > 1024) {
+    p.eg /= 2;
+    p.ek /= 2;
+  }
+  p.lds = lds_bytes(p.ek, p.eg, nacc);
+  p.nval = nval;
+  p.nacc = nacc;
+  return p;
+}
+
+// Carves the workspace; with base == nullptr only computes the size.
+size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
+  WsCarver c(base);
+  int64_t* hdr = c.take<int64_t>(4);
+  uint32_t* H = c.take<uint32_t>((size_t)p.nparts * p.g1);
+  uint32_t* Off = c.take<uint32_t>((size_t)p.nparts * p.g1);
+  uint32_t* Rp = c.take<uint32_t>(p.nparts);
+  PartInfo* pinfo = c.take<PartInfo>(p.nparts);
+  Item* items = c.take<Item>(p.max_items);
+  uint32_t* pcount = c.take<uint32_t>(p.max_items);
+  int64_t* skey = c.take<int64_t>(p.n);
+  uint32_t* spane = c.take<uint32_t>(p.n);
+  void* sval[kMaxAggs] = {};
+  for (int v = 0; v < p.nval; ++v) sval[v] = c.take<uint64_t>(p.n);
+  int64_t* pkey = c.take<int64_t>(p.n);
+  uint32_t* ppane = c.take<uint32_t>(p.n);
+  uint32_t* pcnt = c.take<uint32_t>(p.n);
+  uint64_t* pacc[kMaxAggs] = {};
+  for (int k = 0; k < p.nacc; ++k) pacc[k] = c.take<uint64_t>(p.n);
+  if (a) {
+    a->hdr = hdr;
+    a->H = H;
+    a->Off = Off;
+    a->Rp = Rp;
+    a->pinfo = pinfo;
+    a->items = items;
+    a->pcount = pcount;
+    a->skey = skey;
+    a->spane = spane;
+    for (int v = 0; v < kMaxAggs; ++v) a->sval[v] = sval[v];
+    a->pkey = pkey;
+    a->ppane = ppane;
+    a->pcnt = pcnt;
+    for (int k = 0; k < kMaxAggs; ++k) a->pacc[k] = pacc[k];
+  }
+  return c.size();
+}
+
+// Resolves the aggregate list into staged value columns and accumulators.
+int resolve_aggs(const lms_batch* in, const lms_proj* projs, int32_t nproj, const lms_agg* aggs, int32_t nagg,
+                 WinArgs* a) {
+  if (nagg < 0 || nagg > kMaxAggs) return set_error(LMS_EINVAL, "nagg %d outside [0, %d]", nagg, kMaxAggs);
+  if (nagg > 0 && !aggs) return set_error(LMS_EINVAL, "aggs is NULL");
+  const int next = in->ncols + (projs ? nproj : 0);
+  a->nagg = nagg;
+  a->nval = 0;
+  a->nacc = 0;
+  for (int k = 0; k < nagg; ++k) {
+    const int fn = aggs[k].fn;
+    if (fn < LMS_COUNT || fn > LMS_AVG) return set_error(LMS_EINVAL, "aggregate %d has bad function %d", k, fn);
+    a->afn[k] = fn;
+    a->aacc[k] = -1;
+    if (fn == LMS_COUNT) continue;
+    const int c = aggs[k].col;
+    if (c < 0 || c >= next) return set_error(LMS_EINVAL, "aggregate %d column %d out of range", k, c);
+    const int dt = c < in->ncols ? in->cols[c].dtype : in->cols[projs[c - in->ncols].src].dtype;
+    if (fn != LMS_AVG && !(dt == LMS_I32 || dt == LMS_I64))
+      return set_error(LMS_EINVAL, "aggregate %d: SUM/MIN/MAX need an integer column", k);
+    int v = -1;
+    for (int j = 0; j < a->nval; ++j)
+      if (a->vcol[j] == c) v = j;
+    if (v < 0) {
+      v = a->nval++;
+      a->vcol[v] = c;
+      a->vdt[v] = dt;
+    }
+    const int s = a->nacc++;
+    a->accfn[s] = fn;
+    a->accval[s] = v;
+    a->aacc[k] = s;
+  }
+  return LMS_OK;
+}
+
+int validate_window(const lms_batch* in, int32_t key_col, const lms_window* w) {
+  if (!in) return set_error(LMS_EINVAL, "input batch is NULL");
+  if (!w) return set_error(LMS_EINVAL, "window is NULL");
+  if (key_col < 0 || key_col >= in->ncols) return set_error(LMS_EINVAL, "key column %d out of range", key_col);
+  if (!in->cols) return set_error(LMS_EINVAL, "cols is NULL");
+  const int kdt = in->cols[key_col].dtype;
+  if (kdt != LMS_I32 && kdt != LMS_I64) return set_error(LMS_EINVAL, "key column must be integer");
+  if (w->ts_col < 0 || w->ts_col >= in->ncols) return set_error(LMS_EINVAL, "ts column %d out of range", w->ts_col);
+  const int tdt = in->cols[w->ts_col].dtype;
+  if (tdt != LMS_I32 && tdt != LMS_I64) return set_error(LMS_EINVAL, "ts column must be integer");
+  if (w->len <= 0 || w->len >= (int64_t(1) << 31)) return set_error(LMS_EINVAL, "window length must be in (0, 2^31)");
+  if (w->slide < 0 || w->slide > w->len) return set_error(LMS_EINVAL, "slide must be in [0, len]");
+  if (in->nrows >= (int64_t(1) << 31)) return set_error(LMS_EINVAL, "micro-batch must have < 2^31 rows");
+  return LMS_OK;
+}
+
+}  // namespace
+}  // namespace lms
+
+using namespace lms;
+
+extern "C" int64_t lms_window_agg_pane_limit(int32_t nagg) {
+  int nacc = std::max(0, std::min<int>(nagg, kMaxAggs));
+  return make_plan(1, 1, nacc).eg;
+}
+
+extern "C" size_t lms_window_agg_workspace(const lms_batch* in, int32_t key_col, const lms_window* w,
+                                           const lms_agg* aggs, int32_t nagg) {
+  if (validate_window(in, key_col, w) != LMS_OK) return 0;
+  WinArgs a{};
+  // projections are not known here: every value column is sized at 8 bytes.
+  int nval = 0, nacc = 0;
+  if (nagg > 0 && aggs) {
+    int cols[kMaxAggs];
+    for (int k = 0; k < nagg && k < kMaxAggs; ++k) {
+      if (aggs[k].fn == LMS_COUNT) continue;
+      ++nacc;
+      bool seen = false;
+      for (int j = 0; j < nval; ++j) seen |= cols[j] == aggs[k].col;
+      if (!seen) cols[nval++] = aggs[k].col;
+    }
+  }
+  (void)a;
+  return carve_workspace(make_plan(in->nrows, nval, nacc), nullptr, nullptr);
+}
+
+extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs,
+                              int32_t nproj, int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg,
+                              const lms_groups* out, int64_t* d_count, void* workspace, size_t ws_bytes,
+                              lms_stream stream) {
+  int rc = validate_window(in, key_col, w);
+  if (rc) return rc;
+  WinArgs a{};
+  rc = build_query(in, preds, npred, projs, nproj, &a.q);
+  if (rc) return rc;
+  rc = resolve_aggs(in, projs, nproj, aggs, nagg, &a);
+  if (rc) return rc;
+  if (!out) return set_error(LMS_EINVAL, "output groups is NULL");
+  if (out->cap < 0) return set_error(LMS_EINVAL, "negative output capacity");
+  if (out->cap > 0 && (!out->key || !out->wstart)) return set_error(LMS_EINVAL, "output key/wstart is NULL");
+  if (nagg > 0 && !out->aggs) return set_error(LMS_EINVAL, "output aggs is NULL");
+  for (int k = 0; k < nagg; ++k)
+    if (out->cap > 0 && !out->aggs[k]) return set_error(LMS_EINVAL, "output aggregate %d is NULL", k);
+  if (!d_count) return set_error(LMS_EINVAL, "d_count is NULL");
+
+  const Plan p = make_plan(in->nrows, a.nval, a.nacc);
+  const size_t need = carve_workspace(p, nullptr, nullptr);
+  if (!workspace || ws_bytes < need)
+    return set_error(LMS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
+  carve_workspace(p, workspace, &a);
+
+  a.key_col = key_col;
+  a.ts_col = w->ts_col;
+  a.len = w->len;
+  a.slide = w->slide == 0 ? w->len : w->slide;
+  a.origin = w->origin;
+  a.pane = gcd64(a.len, a.slide);
+  a.R = a.slide / a.pane;
+  a.W = a.len / a.pane;
+  a.inv_pane = 1.0 / (double)a.pane;
+  a.inv_R = 1.0 / (double)a.R;
+  a.pbits = p.pbits;
+  a.nparts = p.nparts;
+  a.g1 = p.g1;
+  a.max_items = p.max_items;
+  a.ek = p.ek;
+  a.eg = p.eg;
+  a.chunk = p.chunk;
+  a.rs = p.rs;
+  a.okey = out->key;
+  a.ows = out->wstart;
+  for (int k = 0; k < nagg; ++k) a.oagg[k] = out->aggs[k];
+  a.cap = out->cap;
+  a.d_count = d_count;
+
+  hipStream_t st = (hipStream_t)stream;
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)k_wa_agg, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+    (void)hipFuncSetAttribute((const void*)k_wa_merge, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+    attr_done = true;
+  }
+  LMS_LAUNCH("k_wa_init", k_wa_init, dim3(1), dim3(64), 0, st, a);
+  if (in->nrows > 0) {
+    const size_t plds = (size_t)p.nparts * 4;
+    LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(p.g1), dim3(kScanTPB), plds, st, a);
+    LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
+    LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
+    LMS_LAUNCH("k_wa_scatter", k_wa_scatter, dim3(p.g1), dim3(kScanTPB), plds, st, a);
+    LMS_LAUNCH("k_wa_agg", k_wa_agg, dim3(p.max_items), dim3(kAggTPB), p.lds, st, a);
+    LMS_LAUNCH("k_wa_merge", k_wa_merge, dim3(p.nparts), dim3(kAggTPB), p.lds, st, a);
+  }
+  return check_hip(hipGetLastError(), "window_agg launch");
+}

@@ -1,0 +1,387 @@
+"""ctypes binding of liblms.so (include/lms.h).
+
+Argument marshalling only: every step of the operators runs in the library's
+HIP kernels.  torch tensors supply device memory and streams.  Importing this
+module loads the library and raises ImportError if it has not been built
+(``python -m paper_2111_04289_amd.build``); there is no fallback path.
+
+The functions named like the C entry points (``lms_filter_project``,
+``lms_window_agg``, ``lms_join_build``, ``lms_hash_join``, ``lms_plan``) take
+torch tensors and plain Python values; they enqueue work on the current (or
+given) stream and return device tensors without synchronising.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblms.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2111_04289_amd.build`")
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- constants (lms.h) ------------------------------------------------------
+LMS_OK, LMS_EINVAL, LMS_EHIP, LMS_ENOMEM, LMS_ECAPACITY, LMS_ERANGE = 0, -1, -2, -3, -4, -5
+I32, I64, F32, F64 = 0, 1, 2, 3
+LT, LE, GT, GE, EQ, NE = 0, 1, 2, 3, 4, 5
+COUNT, SUM, MIN, MAX, AVG = 0, 1, 2, 3, 4
+OP_AGG, OP_FILTER, OP_SHUFFLE, OP_PROJECT, OP_JOIN, OP_EXPAND, OP_SCAN, OP_SORT = range(8)
+DEV_CPU, DEV_GPU = 0, 1
+PLAN_ANALYTIC, PLAN_LEARNED = 0, 1
+
+_TORCH_DT = {torch.int32: I32, torch.int64: I64, torch.float32: F32, torch.float64: F64}
+_DT_TORCH = {v: k for k, v in _TORCH_DT.items()}
+
+
+class LmsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lms error {code}: {msg}")
+        self.code = code
+
+
+# ---- ABI structs ---------------------------------------------------------------
+class lms_col(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lms_batch(ctypes.Structure):
+    _fields_ = [("cols", ctypes.POINTER(lms_col)), ("ncols", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nrows", ctypes.c_int64)]
+
+
+class lms_pred(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("op", ctypes.c_int32), ("ival", ctypes.c_int64), ("fval", ctypes.c_double)]
+
+
+class lms_proj(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int32), ("reserved", ctypes.c_int32), ("mul", ctypes.c_int64),
+                ("add", ctypes.c_int64)]
+
+
+class lms_window(ctypes.Structure):
+    _fields_ = [("ts_col", ctypes.c_int32), ("reserved", ctypes.c_int32), ("len", ctypes.c_int64),
+                ("slide", ctypes.c_int64), ("origin", ctypes.c_int64)]
+
+
+class lms_agg(ctypes.Structure):
+    _fields_ = [("fn", ctypes.c_int32), ("col", ctypes.c_int32)]
+
+
+class lms_groups(ctypes.Structure):
+    _fields_ = [("key", ctypes.c_void_p), ("wstart", ctypes.c_void_p), ("aggs", ctypes.POINTER(ctypes.c_void_p)),
+                ("cap", ctypes.c_int64)]
+
+
+class lms_op_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("base_cost", ctypes.c_double)]
+
+
+class lms_batch_stats(ctypes.Structure):
+    _fields_ = [("batch_bytes", ctypes.c_int64), ("num_cores", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("selectivity", ctypes.c_double), ("distinct_keys", ctypes.c_int64)]
+
+
+class lms_cost_params(ctypes.Structure):
+    _fields_ = [("infpt_bytes", ctypes.c_double), ("base_trans", ctypes.c_double), ("mode", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("model", ctypes.c_void_p)]
+
+
+class lms_trace_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
+
+
+_P = ctypes.POINTER
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_SIGS = {
+    "lms_abi_version": (ctypes.c_int, []),
+    "lms_last_error": (ctypes.c_char_p, []),
+    "lms_filter_project_workspace": (_sz, [_i64]),
+    "lms_filter_project": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(ctypes.c_int32), _i32, _P(lms_proj),
+                                          _i32, _P(lms_batch), _vp, _vp, _sz, _vp]),
+    "lms_window_agg_workspace": (_sz, [_P(lms_batch), _i32, _P(lms_window), _P(lms_agg), _i32]),
+    "lms_window_agg_pane_limit": (_i64, [_i32]),
+    "lms_window_agg": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _i32, _P(lms_window),
+                                      _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz, _vp]),
+    "lms_join_build": (ctypes.c_int, [_P(lms_batch), _i32, _i32, _P(_vp), _vp]),
+    "lms_join_max_mult": (_i64, [_vp]),
+    "lms_join_build_rows": (_i64, [_vp]),
+    "lms_join_free": (None, [_vp]),
+    "lms_hash_join_workspace": (_sz, [_i64]),
+    "lms_hash_join": (ctypes.c_int, [_vp, _P(lms_batch), _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "lms_trace_enable": (ctypes.c_int, [_i32]),
+    "lms_trace_read": (ctypes.c_int, [_P(lms_trace_stat), _i32]),
+    "lms_table2_base_cost": (ctypes.c_double, [_i32]),
+    "lms_plan": (ctypes.c_int, [_P(lms_op_desc), _i32, _P(lms_batch_stats), _P(lms_cost_params), _P(ctypes.c_int32),
+                                _P(ctypes.c_double)]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+ABI_SYMBOLS = tuple(_SIGS)
+
+
+def last_error() -> str:
+    return (_lib.lms_last_error() or b"").decode()
+
+
+def _check(rc: int):
+    if rc != LMS_OK:
+        raise LmsError(rc, last_error())
+
+
+def _stream_handle(stream) -> int:
+    if isinstance(stream, int):  # a raw hipStream_t handle
+        return stream
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class _Batch:
+    """Keeps the ctypes column array alive alongside the lms_batch."""
+
+    def __init__(self, cols: Sequence[torch.Tensor], nrows: int | None = None):
+        self.tensors = list(cols)
+        n = {int(t.shape[0]) for t in self.tensors}
+        if nrows is None:
+            if len(n) > 1:
+                raise ValueError("columns differ in length")
+            nrows = n.pop() if n else 0
+        for t in self.tensors:
+            if t.dim() != 1 or not t.is_contiguous() or t.dtype not in _TORCH_DT:
+                raise ValueError("columns must be contiguous 1-D int32/int64/float32/float64 tensors")
+        self.arr = (lms_col * max(1, len(self.tensors)))()
+        for i, t in enumerate(self.tensors):
+            self.arr[i].data = t.data_ptr()
+            self.arr[i].dtype = _TORCH_DT[t.dtype]
+        self.batch = lms_batch(self.arr, len(self.tensors), 0, nrows)
+
+
+def _preds(preds):
+    preds = list(preds)
+    arr = (lms_pred * max(1, len(preds)))()
+    for i, p in enumerate(preds):
+        col, op, ival = p[0], p[1], p[2]
+        fval = p[3] if len(p) > 3 else float(ival)
+        arr[i] = lms_pred(col, op, int(ival), float(fval))
+    return arr, len(preds)
+
+
+def _projs(projs):
+    projs = list(projs)
+    arr = (lms_proj * max(1, len(projs)))()
+    for i, (src, mul, add) in enumerate(projs):
+        arr[i] = lms_proj(src, 0, int(mul), int(add))
+    return arr, len(projs)
+
+
+class Workspace:
+    """A grow-only device scratch buffer for the operators."""
+
+    def __init__(self, device=None):
+        self.device = device or torch.device("cuda")
+        self.buf = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if self.buf.numel() < nbytes:
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+_default_ws: dict = {}
+
+
+def _ws(workspace, nbytes, device):
+    if workspace is None:
+        workspace = _default_ws.setdefault(str(device), Workspace(device))
+    return workspace.get(nbytes)
+
+
+# ---- filter + project -------------------------------------------------------------
+
+def lms_filter_project(cols, preds=(), keep=(), projs=(), out=None, workspace=None, stream=None):
+    """Enqueues filter+project; returns (out_cols, d_count) with out_cols sized n."""
+    b = _Batch(cols)
+    n = b.batch.nrows
+    dev = cols[0].device if cols else torch.device("cuda")
+    keep = list(keep)
+    projs = list(projs)
+    if out is None:
+        out = [torch.empty(n, dtype=cols[c].dtype, device=dev) for c in keep]
+        out += [torch.empty(n, dtype=cols[p[0]].dtype, device=dev) for p in projs]
+    ob = _Batch(out, nrows=n)
+    pa, npred = _preds(preds)
+    pr, nproj = _projs(projs)
+    ka = (ctypes.c_int32 * max(1, len(keep)))(*keep)
+    d_count = torch.zeros(2, dtype=torch.int64, device=dev)
+    need = _lib.lms_filter_project_workspace(n)
+    ws = _ws(workspace, need, dev)
+    rc = _lib.lms_filter_project(ctypes.byref(b.batch), pa, npred, ka, len(keep), pr, nproj, ctypes.byref(ob.batch),
+                                 d_count.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    _check(rc)
+    return out, d_count
+
+
+# ---- windowed group-by ---------------------------------------------------------------
+
+@dataclass
+class Window:
+    ts_col: int
+    length: int
+    slide: int = 0
+    origin: int = 0
+
+    def c(self):
+        return lms_window(self.ts_col, 0, self.length, self.slide, self.origin)
+
+
+def lms_window_agg_workspace(cols, key_col, window: Window, aggs) -> int:
+    b = _Batch(cols)
+    aa = (lms_agg * max(1, len(aggs)))(*[lms_agg(f, c) for f, c in aggs])
+    w = window.c()
+    return int(_lib.lms_window_agg_workspace(ctypes.byref(b.batch), key_col, ctypes.byref(w), aa, len(aggs)))
+
+
+def pane_limit(nagg: int) -> int:
+    return int(_lib.lms_window_agg_pane_limit(nagg))
+
+
+class Groups:
+    """Device output columns of lms_window_agg."""
+
+    def __init__(self, cap: int, aggs, device):
+        self.cap = cap
+        self.key = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+        self.wstart = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+        self.aggs = [torch.empty(max(cap, 1), dtype=torch.float64 if f == AVG else torch.int64, device=device)
+                     for f, _ in aggs]
+        self._ptrs = (ctypes.c_void_p * max(1, len(self.aggs)))(*[t.data_ptr() for t in self.aggs])
+        self.c = lms_groups(self.key.data_ptr(), self.wstart.data_ptr(), self._ptrs, cap)
+
+
+def lms_window_agg(cols, key_col, window: Window, aggs, preds=(), projs=(), groups: Groups | None = None,
+                   cap: int | None = None, d_count=None, workspace=None, stream=None):
+    """Enqueues the windowed group-by; returns (groups, d_count)."""
+    b = _Batch(cols)
+    n = b.batch.nrows
+    dev = cols[0].device
+    aggs = list(aggs)
+    if groups is None:
+        if cap is None:
+            slide = window.slide or window.length
+            cap = n * (-(-window.length // slide))  # provable bound: each row is in ceil(len/slide) windows
+        groups = Groups(cap, aggs, dev)
+    if d_count is None:
+        d_count = torch.zeros(2, dtype=torch.int64, device=dev)
+    pa, npred = _preds(preds)
+    pr, nproj = _projs(projs)
+    aa = (lms_agg * max(1, len(aggs)))(*[lms_agg(f, c) for f, c in aggs])
+    w = window.c()
+    need = _lib.lms_window_agg_workspace(ctypes.byref(b.batch), key_col, ctypes.byref(w), aa, len(aggs))
+    ws = _ws(workspace, need, dev)
+    rc = _lib.lms_window_agg(ctypes.byref(b.batch), pa, npred, pr, nproj, key_col, ctypes.byref(w), aa, len(aggs),
+                             ctypes.byref(groups.c), d_count.data_ptr(), ws.data_ptr(), ws.numel(),
+                             _stream_handle(stream))
+    _check(rc)
+    return groups, d_count
+
+
+# ---- stream-static join ------------------------------------------------------------------
+
+class JoinTable:
+    def __init__(self, handle: int, keys: torch.Tensor, payload: torch.Tensor):
+        self.handle = ctypes.c_void_p(handle)
+        self._keep = (keys, payload)  # inputs stay alive until the build completed
+
+    def max_mult(self) -> int:
+        m = int(_lib.lms_join_max_mult(self.handle))
+        if m < 0:
+            raise LmsError(m, last_error())
+        return m
+
+    def free(self):
+        if self.handle:
+            _lib.lms_join_free(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lms_join_build(keys: torch.Tensor, payload: torch.Tensor, stream=None) -> JoinTable:
+    b = _Batch([keys, payload])
+    h = ctypes.c_void_p(0)
+    rc = _lib.lms_join_build(ctypes.byref(b.batch), 0, 1, ctypes.byref(h), _stream_handle(stream))
+    _check(rc)
+    return JoinTable(h.value, keys, payload)
+
+
+def lms_hash_join(table: JoinTable, probe_keys: torch.Tensor, cap: int | None = None, out=None, d_count=None,
+                  workspace=None, stream=None):
+    """Enqueues the probe; returns (probe_idx uint32 as int32 tensor, payload, d_count)."""
+    b = _Batch([probe_keys])
+    n = b.batch.nrows
+    dev = probe_keys.device
+    if cap is None:
+        cap = n * max(1, table.max_mult())
+    if out is None:
+        out = (torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(cap, 1), dtype=torch.int32, device=dev))
+    if d_count is None:
+        d_count = torch.zeros(2, dtype=torch.int64, device=dev)
+    need = _lib.lms_hash_join_workspace(n)
+    ws = _ws(workspace, need, dev)
+    rc = _lib.lms_hash_join(table.handle, ctypes.byref(b.batch), 0, out[0].data_ptr(), out[1].data_ptr(), cap,
+                            d_count.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    _check(rc)
+    return out[0], out[1], d_count
+
+
+# ---- kernel tracing ----------------------------------------------------------------------
+
+def lms_trace_enable(on: bool = True):
+    _check(_lib.lms_trace_enable(1 if on else 0))
+
+
+def lms_trace_read() -> dict:
+    """Per-kernel {name: (launches, total_ms, min_ms, max_ms)} since the last read (synchronises)."""
+    buf = (lms_trace_stat * 64)()
+    n = _lib.lms_trace_read(buf, 64)
+    if n < 0:
+        raise LmsError(n, last_error())
+    return {buf[i].name.decode(): (int(buf[i].launches), buf[i].total_ms, buf[i].min_ms, buf[i].max_ms)
+            for i in range(min(n, 64))}
+
+
+# ---- placement --------------------------------------------------------------------------
+
+def table2_base_cost(kind: int) -> float:
+    return float(_lib.lms_table2_base_cost(kind))
+
+
+def lms_plan(kinds, batch_bytes, num_cores, infpt_bytes=150.0 * 1024, base_trans=0.1, base_costs=None,
+             rows=0, selectivity=1.0, distinct_keys=0, mode=PLAN_ANALYTIC, model=None):
+    """MapDevice (Algorithm 2) over the chain `kinds`; returns (devices, costs)."""
+    kinds = list(kinds)
+    n = len(kinds)
+    ops = (lms_op_desc * max(1, n))()
+    for i, k in enumerate(kinds):
+        ops[i] = lms_op_desc(k, 0, float(base_costs[i]) if base_costs is not None else 0.0)
+    st = lms_batch_stats(int(batch_bytes), int(num_cores), 0, int(rows), float(selectivity), int(distinct_keys))
+    cp = lms_cost_params(float(infpt_bytes), float(base_trans), mode, 0, model)
+    dev = (ctypes.c_int32 * max(1, n))()
+    cost = (ctypes.c_double * max(1, n))()
+    _check(_lib.lms_plan(ops, n, ctypes.byref(st), ctypes.byref(cp), dev, cost))
+    return list(dev)[:n], list(cost)[:n]

@@ -1,0 +1,256 @@
+"""GPU parity: the HIP operators (through the C-ABI) against the CPU oracle.
+
+Integer results must be bit-exact; AVG within 1e-5 relative.  Sizes span
+several tiles, partitions and pieces with ragged tails; edge cases cover empty
+inputs, empty filters, hot keys, key values equal to the table's empty marker,
+LDS overflow of a partition, output capacity below the group count, and a key
+with more panes than one workgroup table holds.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import assert_window_equal, gpu_window_agg, log, to_dev
+from oracle import AVG, COUNT, GE, LE, LT, MAX, MIN, NE, SUM
+from paper_2111_04289_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lms():
+    from paper_2111_04289_amd import lms as m
+    return m
+
+
+def rand_cols(seed, n, nkeys, tspan, key64=True, neg=False, zipf=False):
+    rng = np.random.default_rng(seed)
+    lo = -tspan if neg else 0
+    ts = rng.integers(lo, tspan, n, dtype=np.int64)
+    if zipf:
+        key = datagen.zipf_keys(rng, n, 1.1, nkeys)
+    elif key64:
+        key = datagen.splitmix64(rng.integers(0, nkeys, n).astype(np.uint64)).view(np.int64)
+    else:
+        key = rng.integers(0, nkeys, n, dtype=np.int32)
+    val = rng.integers(-1000, 1000, n, dtype=np.int32)
+    f = rng.standard_normal(n).astype(np.float32)
+    return [ts, key, val, f]
+
+
+# ---------------------------------------------------------------- filter + project
+
+@pytest.mark.parametrize("n,seed", [(0, 0), (1, 1), (4095, 2), (4097, 3), (70001, 4), (300000, 5)])
+def test_filter_project_parity(lms, n, seed):
+    log(f"filter_project n={n} seed={seed}")
+    cols = rand_cols(seed, n, 50, 1000, neg=True)
+    cols[3][::97] = np.nan
+    preds = [(2, LT, 300), (3, NE, 0, 0.5)]
+    keep = [0, 1, 3]
+    projs = [(2, 2, 0), (0, -3, 11)]
+    out, d = lms.lms_filter_project(to_dev(cols), preds, keep, projs)
+    torch.cuda.synchronize()
+    m, status = [int(x) for x in d.cpu()]
+    assert status == 0
+    exp = oracle.filter_project(cols, preds, keep, projs)
+    assert m == len(exp[0])
+    for j in range(len(exp)):
+        g = out[j][:m].cpu().numpy()
+        if g.dtype.kind == "f":
+            np.testing.assert_array_equal(np.isnan(g), np.isnan(exp[j]))
+            np.testing.assert_array_equal(g[~np.isnan(g)], exp[j][~np.isnan(exp[j])])
+        else:
+            np.testing.assert_array_equal(g, exp[j])
+
+
+def test_filter_project_all_and_none(lms):
+    cols = rand_cols(9, 10000, 10, 100)
+    for preds, expect in [([], 10000), ([(2, GE, 5000)], 0), ([(2, LE, 5000)], 10000)]:
+        out, d = lms.lms_filter_project(to_dev(cols), preds, [0, 2], [])
+        torch.cuda.synchronize()
+        assert int(d[0]) == expect
+        if expect:
+            np.testing.assert_array_equal(out[1][:expect].cpu().numpy(), cols[2])
+
+
+# ---------------------------------------------------------------- windowed group-by
+
+AGGS5 = [(COUNT, 0), (SUM, 2), (MIN, 2), (MAX, 2), (AVG, 3)]
+
+
+def test_config0_tumbling_exact():
+    cols = datagen.config0()
+    aggs = [(COUNT, 0), (SUM, 4)]
+    preds, projs = [(2, LT, 500)], [(2, 2, 0)]
+    log("config0 tumbling")
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 1000, 0, 0, aggs, preds, projs)
+    assert status == 0
+    exp = oracle.window_agg(cols, 1, 0, 1000, 0, 0, aggs, preds, projs)
+    assert cnt == len(exp["key"])
+    assert_window_equal(got, exp, aggs, "config0")
+
+
+@pytest.mark.parametrize("n,length,slide,origin,key64,neg,nkeys,tspan", [
+    (1, 10, 0, 0, True, False, 5, 100),
+    (1000, 10, 3, 5, True, True, 7, 200),
+    (50000, 10000, 1000, 0, True, False, 3000, 60000),
+    (123457, 3000, 1000, -250, False, True, 500, 20000),
+    (200003, 1000, 400, 17, True, False, 20000, 30000),
+    (65536, 7, 7, 0, False, False, 1024, 10000),
+    (300000, 60, 5, 3, True, True, 100000, 3000),
+])
+def test_window_agg_parity(n, length, slide, origin, key64, neg, nkeys, tspan):
+    log(f"window_agg n={n} L={length} S={slide} origin={origin}")
+    cols = rand_cols(n, n, nkeys, tspan, key64=key64, neg=neg)
+    preds = [(2, LT, 600)]
+    projs = [(2, 3, -7)]
+    aggs = AGGS5 + [(SUM, 4), (MIN, 4)]
+    got, cnt, status = gpu_window_agg(cols, 1, 0, length, slide, origin, aggs, preds, projs)
+    assert status == 0
+    exp = oracle.window_agg(cols, 1, 0, length, slide, origin, aggs, preds, projs)
+    assert cnt == len(exp["key"])
+    assert_window_equal(got, exp, aggs, f"n={n}")
+
+
+def test_window_agg_zipf_hot_keys_pieces_and_merge():
+    # one hot key carries ~12% of the rows: its partition is split into pieces and merged
+    n = 1_000_000
+    cols = datagen.config1(n)
+    log("zipf 1M sliding")
+    preds = [(2, LT, datagen.CONFIG1_VAL_CUT)]
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 10000, 1000, 0, AGGS5, preds)
+    assert status == 0
+    exp = oracle.window_agg(cols, 1, 0, 10000, 1000, 0, AGGS5, preds)
+    assert_window_equal(got, exp, AGGS5, "zipf")
+
+
+def test_window_agg_single_key_many_rows():
+    n = 300000
+    rng = np.random.default_rng(3)
+    cols = [rng.integers(0, 5000, n, dtype=np.int64), np.full(n, 42, np.int64),
+            rng.integers(0, 100, n, dtype=np.int32), rng.standard_normal(n).astype(np.float32)]
+    log("single key")
+    for length, slide in [(1000, 0), (1000, 250)]:
+        got, cnt, status = gpu_window_agg(cols, 1, 0, length, slide, 0, AGGS5)
+        assert status == 0
+        assert_window_equal(got, oracle.window_agg(cols, 1, 0, length, slide, 0, AGGS5), AGGS5, f"{length}/{slide}")
+
+
+def test_window_agg_lds_overflow_splits_partition():
+    # all-distinct keys: each partition holds far more groups than the LDS tables
+    n = 400000
+    rng = np.random.default_rng(4)
+    cols = [rng.integers(0, 4000, n, dtype=np.int64), rng.permutation(n).astype(np.int64) * 7919 - 10**12,
+            rng.integers(0, 100, n, dtype=np.int32), rng.standard_normal(n).astype(np.float32)]
+    log("distinct keys")
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 1000, 500, 0, AGGS5)
+    assert status == 0
+    assert_window_equal(got, oracle.window_agg(cols, 1, 0, 1000, 500, 0, AGGS5), AGGS5, "distinct")
+
+
+def test_window_agg_sentinel_and_extreme_keys():
+    n = 20000
+    rng = np.random.default_rng(5)
+    special = np.array([np.iinfo(np.int64).min, np.iinfo(np.int64).max, 0, -1], np.int64)
+    cols = [rng.integers(-5000, 5000, n, dtype=np.int64), special[rng.integers(0, 4, n)],
+            rng.integers(-2**31, 2**31 - 1, n, dtype=np.int64).astype(np.int32), rng.standard_normal(n).astype(np.float32)]
+    log("sentinel keys")
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 300, 100, -1, AGGS5)
+    assert status == 0
+    assert_window_equal(got, oracle.window_agg(cols, 1, 0, 300, 100, -1, AGGS5), AGGS5, "sentinel")
+
+
+def test_window_agg_empty_and_filtered_out():
+    cols = rand_cols(1, 0, 5, 100)
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 10, 5, 0, AGGS5, cap=16)
+    assert (cnt, status) == (0, 0)
+    cols = rand_cols(2, 5000, 5, 100)
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 10, 5, 0, AGGS5, preds=[(2, GE, 10**6)], cap=16)
+    assert (cnt, status) == (0, 0)
+
+
+def test_window_agg_capacity_below_count():
+    cols = rand_cols(6, 50000, 300, 5000)
+    exp = oracle.window_agg(cols, 1, 0, 100, 50, 0, AGGS5)
+    total = len(exp["key"])
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 100, 50, 0, AGGS5, cap=total // 3)
+    assert status == 0 and cnt == total
+    # every written row is a correct group
+    ek = {(int(w), int(k)): i for i, (w, k) in enumerate(zip(exp["wstart"], exp["key"]))}
+    for r in range(len(got["key"])):
+        i = ek[(int(got["wstart"][r]), int(got["key"][r]))]
+        assert int(got["aggs"][0][r]) == int(exp["aggs"][0][i])
+
+
+def test_window_agg_key_with_too_many_panes_reports_capacity():
+    from paper_2111_04289_amd import lms
+    limit = lms.pane_limit(len(AGGS5))
+    n = 4 * limit
+    cols = [np.arange(n, dtype=np.int64), np.zeros(n, np.int64), np.ones(n, np.int32), np.zeros(n, np.float32)]
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 1, 0, 0, AGGS5)  # tumbling 1 ms: one pane per row, one key
+    assert status == lms.LMS_ECAPACITY
+
+
+def test_window_agg_int32_key_and_ts():
+    n = 100000
+    rng = np.random.default_rng(8)
+    cols = [rng.integers(-100000, 100000, n, dtype=np.int32), rng.integers(0, 900, n, dtype=np.int32),
+            rng.integers(0, 100, n, dtype=np.int32), rng.random(n, dtype=np.float32)]
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 5000, 2500, 0, AGGS5)
+    assert status == 0
+    assert_window_equal(got, oracle.window_agg(cols, 1, 0, 5000, 2500, 0, AGGS5), AGGS5, "int32")
+
+
+def test_window_agg_is_deterministic_on_integers():
+    cols = datagen.config1(400000)
+    aggs = [(COUNT, 0), (SUM, 2), (MIN, 2), (MAX, 2)]
+    a, _, _ = gpu_window_agg(cols, 1, 0, 10000, 1000, 0, aggs)
+    b, _, _ = gpu_window_agg(cols, 1, 0, 10000, 1000, 0, aggs)
+    assert_window_equal(a, b, aggs, "repeat")
+
+
+# ---------------------------------------------------------------- join
+
+@pytest.mark.parametrize("nb,npr,dup,kdt", [(0, 100, False, np.int64), (1000, 0, False, np.int64),
+                                            (1 << 12, 50000, False, np.int64), (5000, 70001, True, np.int64),
+                                            (3000, 40000, True, np.int32)])
+def test_hash_join_parity(lms, nb, npr, dup, kdt):
+    log(f"join nb={nb} np={npr} dup={dup}")
+    if dup:
+        bk, bp = datagen.static_table_dup(nb, max(1, nb // 2))
+    else:
+        bk, bp = datagen.static_table(nb)
+    pk = datagen.zipf_keys(np.random.default_rng(7), npr, 1.1, max(1, nb))
+    if kdt == np.int32:
+        bk = (bk & 0x7FFF).astype(np.int32)
+        pk = (pk & 0x7FFF).astype(np.int32)
+    t = lms.lms_join_build(torch.from_numpy(bk).cuda(), torch.from_numpy(bp).cuda())
+    mult = t.max_mult()
+    if nb:
+        assert mult == int(np.unique(bk, return_counts=True)[1].max())
+    idx, pay, d = lms.lms_hash_join(t, torch.from_numpy(pk).cuda())
+    torch.cuda.synchronize()
+    m, status = [int(x) for x in d.cpu()]
+    assert status == 0
+    ei, ep = oracle.hash_join(bk, bp, pk)
+    assert m == len(ei)
+    gi = idx[:m].cpu().numpy().astype(np.uint32).astype(np.int64)
+    gp = pay[:m].cpu().numpy()
+    np.testing.assert_array_equal(gi, ei)  # grouped by ascending probe row
+    o1 = np.lexsort((gp, gi))
+    o2 = np.lexsort((ep, ei))
+    np.testing.assert_array_equal(gp[o1], ep[o2])
+    t.free()
+
+
+def test_hash_join_capacity_below_count(lms):
+    bk, bp = datagen.static_table(1024)
+    pk = np.tile(bk, 5)
+    t = lms.lms_join_build(torch.from_numpy(bk).cuda(), torch.from_numpy(bp).cuda())
+    idx, pay, d = lms.lms_hash_join(t, torch.from_numpy(pk).cuda(), cap=100)
+    torch.cuda.synchronize()
+    assert int(d[0]) == len(pk)
+    ei, ep = oracle.hash_join(bk, bp, pk)
+    np.testing.assert_array_equal(idx[:100].cpu().numpy(), ei[:100])
+    np.testing.assert_array_equal(pay[:100].cpu().numpy(), ep[:100])

@@ -2,9 +2,9 @@
 // stream compaction of the rows that pass a conjunction of predicates.
 //
 // Three launches: per-tile counts of passing rows, one scan of the tile
-// counts, then a write pass in which every round of TPB consecutive rows gets
-// its output ranks from a wave ballot/prefix and a block prefix, so rows keep
-// their input order without any global atomic.
+// counts, then a write pass that ranks each round of rows with a block prefix
+// and stages them in LDS, so rows keep their input order without any global
+// atomic and the output writes are coalesced.
 #include <algorithm>
 
 #include "lms_internal.h"
@@ -14,6 +14,7 @@ namespace {
 
 constexpr int kTPB = 256;
 constexpr int kScanThreads = 1024;
+constexpr int kRows = 4;
 
 struct FpArgs {
   Query q;
@@ -28,12 +29,26 @@ struct FpArgs {
   int64_t* d_count;
 };
 
+// Each thread owns kRows consecutive rows of a round of kTPB * kRows rows, so
+// its predicate loads are contiguous and a block prefix over per-thread counts
+// ranks the passing rows in input order.
 __global__ __launch_bounds__(kTPB) void k_fp_count(FpArgs a) {
   __shared__ uint32_t scratch[kTPB / 64 + 1];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   uint32_t c = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kTPB) c += row_passes(a.q, i) ? 1u : 0u;
+  for (int64_t b = lo + (int64_t)threadIdx.x * kRows; b < hi; b += (int64_t)kTPB * kRows) {
+    int64_t idx[kRows];
+    bool ok[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+      idx[u] = b + u;
+      ok[u] = idx[u] < hi;
+    }
+    rows_pass<kRows>(a.q, idx, ok);
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) c += ok[u] ? 1u : 0u;
+  }
   c = block_sum<kTPB>(c, scratch);
   if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = c;
 }
@@ -48,37 +63,55 @@ __global__ __launch_bounds__(kScanThreads) void k_fp_scan(FpArgs a) {
   }
 }
 
-__device__ __forceinline__ void store_value(void* col, int dt, int64_t r, const Query& q, int src, int64_t i,
-                                            bool is_proj, int pj) {
-  if (is_proj) {
-    const int64_t v = project(q, pj, i);
-    if (dt == LMS_I32) ((int32_t*)col)[r] = (int32_t)v;
-    else ((int64_t*)col)[r] = v;
-    return;
-  }
-  switch (dt) {
-    case LMS_I32: ((int32_t*)col)[r] = ((const int32_t*)q.col[src])[i]; break;
-    case LMS_I64: ((int64_t*)col)[r] = ((const int64_t*)q.col[src])[i]; break;
-    case LMS_F32: ((float*)col)[r] = ((const float*)q.col[src])[i]; break;
-    default: ((double*)col)[r] = ((const double*)q.col[src])[i]; break;
+// Value of output column j for input row i, as raw 64-bit bits.
+__device__ __forceinline__ uint64_t out_bits(const FpArgs& a, int j, int64_t i) {
+  if (j >= a.nkeep) return (uint64_t)project(a.q, j - a.nkeep, i);
+  const int c = a.keep[j];
+  switch (a.q.dt[c]) {
+    case LMS_I32: return (uint64_t)(uint32_t)((const int32_t*)a.q.col[c])[i];
+    case LMS_F32: return (uint64_t)__float_as_uint(((const float*)a.q.col[c])[i]);
+    default: return ((const uint64_t*)a.q.col[c])[i];
   }
 }
 
+__device__ __forceinline__ void put_bits(void* col, int dt, int64_t r, uint64_t v) {
+  if (dt == LMS_I32 || dt == LMS_F32) ((uint32_t*)col)[r] = (uint32_t)v;
+  else ((uint64_t*)col)[r] = v;
+}
+
+// Stable compaction: the passing rows of a round are ranked, staged column by
+// column in LDS at their rank, and copied out with consecutive threads writing
+// consecutive output rows.
 __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
   __shared__ uint32_t scratch[kTPB / 64 + 1];
+  __shared__ uint64_t stage[kTPB * kRows];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
+  const int ncol = a.nkeep + a.q.nproj;
   int64_t run = a.tile_off[blockIdx.x];
-  for (int64_t b = lo; b < hi; b += kTPB) {
-    const int64_t i = b + threadIdx.x;
-    const bool pass = i < hi && row_passes(a.q, i);
+  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kRows) {
+    const int64_t b = b0 + (int64_t)threadIdx.x * kRows;
+    bool pass[kRows];
+    int64_t idx[kRows];
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) {
+      idx[u] = b + u;
+      pass[u] = idx[u] < hi;
+    }
+    rows_pass<kRows>(a.q, idx, pass);
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) c += pass[u];
     uint32_t tot;
-    const uint32_t r = block_excl_scan<kTPB>(pass ? 1u : 0u, scratch, &tot);
-    if (pass) {
-      const int64_t o = run + r;
-      for (int j = 0; j < a.nkeep; ++j) store_value(a.out[j], a.odt[j], o, a.q, a.keep[j], i, false, 0);
-      for (int j = 0; j < a.q.nproj; ++j)
-        store_value(a.out[a.nkeep + j], a.odt[a.nkeep + j], o, a.q, a.q.prsrc[j], i, true, j);
+    const uint32_t r0 = block_excl_scan<kTPB>(c, scratch, &tot);
+    for (int j = 0; j < ncol; ++j) {
+      uint32_t r = r0;
+#pragma unroll
+      for (int u = 0; u < kRows; ++u)
+        if (pass[u]) stage[r++] = out_bits(a, j, b + u);
+      __syncthreads();
+      for (uint32_t t = threadIdx.x; t < tot; t += kTPB) put_bits(a.out[j], a.odt[j], run + t, stage[t]);
+      __syncthreads();
     }
     run += tot;
   }
@@ -98,7 +131,7 @@ struct FpPlan {
 
 FpPlan fp_plan(int64_t n) {
   FpPlan p;
-  p.chunk = 4096;
+  p.chunk = 8192;
   while ((n + p.chunk - 1) / p.chunk > 65536) p.chunk *= 2;
   p.ntiles = (int)((n + p.chunk - 1) / p.chunk);
   return p;

@@ -71,6 +71,30 @@ __device__ __forceinline__ bool row_passes(const Query& q, int64_t i) {
   return ok;
 }
 
+// Predicates of U rows at once (rows idx[u] with valid[u]): for each predicate
+// the U loads are issued together, so the rows' memory latencies overlap.
+template <int U>
+__device__ __forceinline__ void rows_pass(const Query& q, const int64_t (&idx)[U], bool (&ok)[U]) {
+  for (int k = 0; k < q.npred; ++k) {
+    const int c = q.pcol[k];
+    const int dt = q.dt[c];
+    const void* col = q.col[c];
+    if (is_int_dtype(dt)) {
+      int64_t v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = ok[u] ? load_i64(col, dt, idx[u]) : 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) ok[u] = ok[u] && compare<int64_t>(v[u], q.pop[k], q.pival[k]);
+    } else {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = ok[u] ? load_f64(col, dt, idx[u]) : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) ok[u] = ok[u] && compare<double>(v[u], q.pop[k], q.pfval[k]);
+    }
+  }
+}
+
 // Projection j of row i, wrapped to the source column's width.
 __device__ __forceinline__ int64_t project(const Query& q, int j, int64_t i) {
   const int s = q.prsrc[j];

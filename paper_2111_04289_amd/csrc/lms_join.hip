@@ -8,7 +8,9 @@
 // from the home slot to the first unused slot.
 // Probe: per-tile match counts, a scan of the tile counts, then a write pass
 // that ranks each round of rows with a block prefix, so the pairs come out
-// grouped by ascending probe row without global atomics.
+// grouped by ascending probe row without global atomics.  Each thread walks
+// the chains of several consecutive rows in lockstep to overlap the random
+// slot reads (the table is MALL-resident, not L2-resident).
 #include <algorithm>
 
 #include "lms_internal.h"
@@ -33,6 +35,8 @@ namespace {
 
 constexpr int kTPB = 256;
 constexpr int kScanThreads = 1024;
+constexpr int kProbe = 4;  // probe rows per thread per round
+constexpr int kHold = 2;   // matches per row held in registers
 
 __global__ void k_jb_clear(JSlot* slots, uint64_t nslots, int64_t* d_mult) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -97,16 +101,38 @@ struct ProbeArgs {
   int64_t* d_count;
 };
 
-__device__ __forceinline__ uint32_t count_matches(const ProbeArgs& a, int64_t k) {
-  uint64_t s = fmix64((uint64_t)k) & a.mask;
-  uint32_t c = 0;
-  for (uint64_t t = 0; t <= a.mask; ++t) {
-    const JSlot sl = a.slots[s];
-    if (!sl.used) break;
-    c += sl.key == k;
-    s = (s + 1) & a.mask;
+// Walks the probe chains of kProbe consecutive rows in lockstep, so their slot
+// loads are independent; calls hit(u, payload) for every match of row u and
+// holds at most kHold payloads per row for the caller.
+template <class F>
+__device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)[kProbe], const bool (&valid)[kProbe],
+                                          F hit) {
+  uint64_t s[kProbe];
+  bool active[kProbe];
+#pragma unroll
+  for (int u = 0; u < kProbe; ++u) {
+    s[u] = fmix64((uint64_t)k[u]) & a.mask;
+    active[u] = valid[u];
   }
-  return c;
+  for (uint64_t t = 0; t <= a.mask; ++t) {
+    bool any = false;
+    JSlot sl[kProbe];
+#pragma unroll
+    for (int u = 0; u < kProbe; ++u)
+      if (active[u]) sl[u] = a.slots[s[u]];
+#pragma unroll
+    for (int u = 0; u < kProbe; ++u) {
+      if (!active[u]) continue;
+      if (!sl[u].used) {
+        active[u] = false;
+        continue;
+      }
+      if (sl[u].key == k[u]) hit(u, sl[u].pay);
+      s[u] = (s[u] + 1) & a.mask;
+      any = true;
+    }
+    if (!any) break;
+  }
 }
 
 __global__ __launch_bounds__(kTPB) void k_jp_count(ProbeArgs a) {
@@ -114,7 +140,16 @@ __global__ __launch_bounds__(kTPB) void k_jp_count(ProbeArgs a) {
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
   uint32_t c = 0;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += kTPB) c += count_matches(a, load_i64(a.pkey, a.kdt, i));
+  for (int64_t b = lo + (int64_t)threadIdx.x * kProbe; b < hi; b += (int64_t)kTPB * kProbe) {
+    int64_t k[kProbe];
+    bool valid[kProbe];
+#pragma unroll
+    for (int u = 0; u < kProbe; ++u) {
+      valid[u] = b + u < hi;
+      k[u] = valid[u] ? load_i64(a.pkey, a.kdt, b + u) : 0;
+    }
+    walk_rows(a, k, valid, [&](int, int32_t) { ++c; });
+  }
   c = block_sum<kTPB>(c, scratch);
   if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = c;
 }
@@ -134,31 +169,59 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
   int64_t run = a.tile_off[blockIdx.x];
-  for (int64_t b = lo; b < hi; b += kTPB) {
-    const int64_t i = b + threadIdx.x;
-    int64_t k = 0;
-    uint32_t c = 0;
-    if (i < hi) {
-      k = load_i64(a.pkey, a.kdt, i);
-      c = count_matches(a, k);
+  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kProbe) {
+    const int64_t b = b0 + (int64_t)threadIdx.x * kProbe;
+    int64_t k[kProbe];
+    bool valid[kProbe];
+    uint32_t cnt[kProbe];
+    int32_t held[kProbe][kHold];
+#pragma unroll
+    for (int u = 0; u < kProbe; ++u) {
+      valid[u] = b + u < hi;
+      k[u] = valid[u] ? load_i64(a.pkey, a.kdt, b + u) : 0;
+      cnt[u] = 0;
+#pragma unroll
+      for (int h = 0; h < kHold; ++h) held[u][h] = 0;
     }
+    walk_rows(a, k, valid, [&](int u, int32_t pay) {
+#pragma unroll
+      for (int h = 0; h < kHold; ++h)
+        if (cnt[u] == (uint32_t)h) held[u][h] = pay;
+      ++cnt[u];
+    });
+    uint32_t c = 0;
+#pragma unroll
+    for (int u = 0; u < kProbe; ++u) c += cnt[u];
     uint32_t tot;
-    const uint32_t r = block_excl_scan<kTPB>(c, scratch, &tot);
-    if (c) {
-      int64_t o = run + r;
-      uint64_t s = fmix64((uint64_t)k) & a.mask;
-      for (uint64_t t = 0; t <= a.mask; ++t) {
-        const JSlot sl = a.slots[s];
-        if (!sl.used) break;
-        if (sl.key == k) {
-          if (o < a.cap) {
-            a.out_idx[o] = (uint32_t)i;
-            a.out_pay[o] = sl.pay;
+    int64_t o = run + block_excl_scan<kTPB>(c, scratch, &tot);
+#pragma unroll
+    for (int u = 0; u < kProbe; ++u) {
+      if (cnt[u] == 0) continue;
+      if (cnt[u] <= (uint32_t)kHold) {
+#pragma unroll
+        for (int h = 0; h < kHold; ++h) {
+          if ((uint32_t)h < cnt[u] && o + h < a.cap) {
+            a.out_idx[o + h] = (uint32_t)(b + u);
+            a.out_pay[o + h] = held[u][h];
           }
-          ++o;
         }
-        s = (s + 1) & a.mask;
+      } else {  // more matches than held: walk this row's chain again
+        int64_t r = o;
+        uint64_t s = fmix64((uint64_t)k[u]) & a.mask;
+        for (uint64_t t = 0; t <= a.mask; ++t) {
+          const JSlot sl = a.slots[s];
+          if (!sl.used) break;
+          if (sl.key == k[u]) {
+            if (r < a.cap) {
+              a.out_idx[r] = (uint32_t)(b + u);
+              a.out_pay[r] = sl.pay;
+            }
+            ++r;
+          }
+          s = (s + 1) & a.mask;
+        }
       }
+      o += cnt[u];
     }
     run += tot;
   }
@@ -178,7 +241,7 @@ struct JpPlan {
 
 JpPlan jp_plan(int64_t n) {
   JpPlan p;
-  p.chunk = 4096;
+  p.chunk = 8192;
   while ((n + p.chunk - 1) / p.chunk > 65536) p.chunk *= 2;
   p.ntiles = (int)((n + p.chunk - 1) / p.chunk);
   return p;

@@ -43,7 +43,7 @@ struct Item {
 };
 
 struct PartInfo {
-  uint32_t first, kp;
+  uint32_t first, kp, start, reserved;
 };
 
 struct WinArgs {
@@ -70,7 +70,7 @@ struct WinArgs {
   uint32_t* Rp;
   PartInfo* pinfo;
   Item* items;
-  uint32_t* pcount;
+  uint32_t* pfill;  // nparts: partial records reserved so far in each split partition
   int64_t* skey;
   uint32_t* spane;
   void* sval[kMaxAggs];
@@ -136,12 +136,14 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
   for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kUnroll) {
     bool ok[kUnroll];
     int64_t key[kUnroll];
+    int64_t idx[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t i = b + (int64_t)u * kScanTPB;
-      ok[u] = i < hi && row_passes(a.q, i);
-      key[u] = i < hi ? load_i64(kc, kdt, i) : 0;
+      idx[u] = b + (int64_t)u * kScanTPB;
+      ok[u] = idx[u] < hi;
+      key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
     }
+    rows_pass<kUnroll>(a.q, idx, ok);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       if (ok[u]) atomicAdd(&hist[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
@@ -201,11 +203,27 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
   if (threadIdx.x == 0) {
     a.pinfo[p].first = ibase;
     a.pinfo[p].kp = kp;
+    a.pinfo[p].start = start;
+    a.pinfo[p].reserved = 0;
+    a.pfill[p] = 0;
     if (p == a.nparts - 1) a.hdr[1] = ibase + kp;
   }
 }
 
+// Raw bits of staged value column v at row i (int64, or the float's own bits).
+__device__ __forceinline__ uint64_t staged_bits(const WinArgs& a, int v, int64_t i) {
+  const int c = a.vcol[v];
+  switch (a.vdt[v]) {
+    case LMS_I32:
+    case LMS_I64: return (uint64_t)ext_i64(a.q, c, i);
+    case LMS_F32: return (uint64_t)__float_as_uint(((const float*)a.q.col[c])[i]);
+    default: return ((const uint64_t*)a.q.col[c])[i];
+  }
+}
+
 // Scatter the passing rows, as (key, pane, value columns), to their partition.
+// Every column a row needs is loaded for all kUnroll rows of a thread before
+// the first LDS cursor atomic, so the loads overlap.
 __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
   extern __shared__ uint32_t cursor[];
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) cursor[p] = a.Off[(size_t)p * a.g1 + blockIdx.x];
@@ -220,18 +238,21 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
   bool range_err = false;
   for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kUnroll) {
     bool ok[kUnroll];
-    int64_t key[kUnroll], ts[kUnroll];
+    int64_t key[kUnroll], ts[kUnroll], idx[kUnroll];
+    uint64_t val[kUnroll][kMaxAggs];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t i = b + (int64_t)u * kScanTPB;
-      ok[u] = i < hi && row_passes(a.q, i);
-      key[u] = i < hi ? load_i64(kc, kdt, i) : 0;
-      ts[u] = i < hi ? load_i64(tc, tdt, i) : 0;
+      idx[u] = b + (int64_t)u * kScanTPB;
+      ok[u] = idx[u] < hi;
+      key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
+      ts[u] = ok[u] ? load_i64(tc, tdt, idx[u]) : 0;
+#pragma unroll
+      for (int v = 0; v < kMaxAggs; ++v) val[u][v] = (ok[u] && v < a.nval) ? staged_bits(a, v, idx[u]) : 0;
     }
+    rows_pass<kUnroll>(a.q, idx, ok);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (!ok[u]) continue;
-      const int64_t i = b + (int64_t)u * kScanTPB;
       const uint32_t pos = atomicAdd(&cursor[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
       const int64_t rel = ts[u] - a.origin - b0 * a.pane;
       uint64_t qp = 0;
@@ -246,13 +267,8 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
 #pragma unroll
       for (int v = 0; v < kMaxAggs; ++v) {
         if (v < a.nval) {
-          const int c = a.vcol[v];
-          switch (a.vdt[v]) {
-            case LMS_I32: ((int32_t*)a.sval[v])[pos] = (int32_t)ext_i64(a.q, c, i); break;
-            case LMS_I64: ((int64_t*)a.sval[v])[pos] = ext_i64(a.q, c, i); break;
-            case LMS_F32: ((float*)a.sval[v])[pos] = ((const float*)a.q.col[c])[i]; break;
-            default: ((double*)a.sval[v])[pos] = ((const double*)a.q.col[c])[i]; break;
-          }
+          if (a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_F32) ((uint32_t*)a.sval[v])[pos] = (uint32_t)val[u][v];
+          else ((uint64_t*)a.sval[v])[pos] = val[u][v];
         }
       }
     }
@@ -269,7 +285,8 @@ struct Lds {
   uint64_t* gid;   // eg: (key slot << 32) | pane, or kEmptyGid
   uint64_t* acc;   // nacc * eg: accumulator k of group g at acc[k * eg + g]
   uint32_t* gcnt;  // eg: rows per group
-  uint32_t* order; // eg: group slots ordered by key
+  uint32_t* order; // eg: group slots ordered by key, then windows per sorted entry
+  uint64_t* sorted; // eg: (pane << 32 | group slot) in key-major, pane-sorted order
   uint32_t* scan;  // kAggTPB / 64 + 1
   uint32_t* misc;  // flags and broadcasts
   uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
@@ -281,7 +298,7 @@ __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   size_t b = 0;
   b += align_up((size_t)(ek + 1) * 8, 16);
   b += 3 * align_up((size_t)(ek + 1) * 4, 16);
-  b += (size_t)eg * 8 + (size_t)nacc * eg * 8 + (size_t)eg * 4 + (size_t)eg * 4;
+  b += (size_t)eg * 8 + (size_t)nacc * eg * 8 + (size_t)eg * 4 + (size_t)eg * 4 + (size_t)eg * 8;
   b += align_up((kAggTPB / 64 + 1) * 4, 16) + M_WORDS * 4;
   b += 2 * kStackCap * 8;
   return b;
@@ -306,6 +323,8 @@ __device__ __forceinline__ Lds carve_lds(char* base, int ek, int eg, int nacc) {
   o += (size_t)eg * 4;
   s.order = (uint32_t*)(base + o);
   o += (size_t)eg * 4;
+  s.sorted = (uint64_t*)(base + o);
+  o += (size_t)eg * 8;
   s.scan = (uint32_t*)(base + o);
   o += align_up((kAggTPB / 64 + 1) * 4, 16);
   s.misc = (uint32_t*)(base + o);
@@ -541,46 +560,17 @@ __device__ __forceinline__ int64_t fdiv(int64_t x, int64_t d, double inv) {
   return q;
 }
 
-// Windows of one key from its pane-sorted groups; calls emit(w, jlo, jhi) for
-// each window w (relative index) that contains the key's panes jlo..jhi.  Pane
-// q lies in windows floor((q - W) / R) + 1 .. floor(q / R).
-template <class F>
-__device__ __forceinline__ uint32_t sweep_windows(const WinArgs& a, const Lds& s, const uint32_t* list, uint32_t m,
-                                                  F emit) {
-  auto pane_at = [&](uint32_t j) { return (int64_t)(uint32_t)s.gid[list[j]]; };
-  auto first_win = [&](int64_t q) { return fdiv(q - a.W, a.R, a.inv_R) + 1; };
-  auto last_win = [&](int64_t q) { return fdiv(q, a.R, a.inv_R); };
-  uint32_t nout = 0, next = 0, jlo = 0;
-  int64_t jhi = -1;
-  int64_t fnext = first_win(pane_at(0));
-  int64_t llo = last_win(pane_at(0));
-  int64_t w = fnext;
-  for (;;) {
-    while (next < m && fnext <= w) {
-      jhi = next;
-      ++next;
-      if (next < m) fnext = first_win(pane_at(next));
-    }
-    while ((int64_t)jlo <= jhi && llo < w) {
-      ++jlo;
-      if (jlo < m) llo = last_win(pane_at(jlo));
-    }
-    if ((int64_t)jlo > jhi) {
-      if (next >= m) break;
-      w = fnext;
-      continue;
-    }
-    emit(w, jlo, (uint32_t)jhi);
-    ++nout;
-    ++w;
-  }
-  return nout;
-}
-
-// Sliding windows: group the (key, pane) entries by key, order each key's
-// panes, then emit every window holding at least one of them.
+// Sliding windows, composed in parallel over the groups of the LDS table.
+// The groups of each key are ranked by pane (every key has at most one group
+// per pane) into key-major, pane-sorted order.  Each window of a key is
+// produced by the first of the key's panes it contains: pane i covers windows
+// first_win(q_i)..last_win(q_i), of which it owns those after the previous
+// pane's last window.  A window's panes are then that owner and the following
+// panes of the key whose first window is not later than it.
 __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   const int nk = a.ek + 1;
+  auto first_win = [&](int64_t q) { return fdiv(q - a.W, a.R, a.inv_R) + 1; };
+  auto last_win = [&](int64_t q) { return fdiv(q, a.R, a.inv_R); };
   for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
     const uint64_t gid = s.gid[g];
     if (gid != kEmptyGid) atomicAdd(&s.kcnt[(uint32_t)(gid >> 32)], 1u);
@@ -588,7 +578,8 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   __syncthreads();
   for (int i = threadIdx.x; i < nk; i += kAggTPB) s.kaux[i] = s.kcnt[i];
   __syncthreads();
-  block_scan_array<kAggTPB>(s.kaux, nk, s.scan);
+  const uint32_t ng = block_scan_array<kAggTPB>(s.kaux, nk, s.scan);  // kaux = start of each key's run
+  if (ng == 0) return;
   for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
     const uint64_t gid = s.gid[g];
     if (gid != kEmptyGid) {
@@ -597,88 +588,93 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
     }
   }
   __syncthreads();
-  for (int kid = threadIdx.x; kid < nk; kid += kAggTPB) {
-    const uint32_t m = s.kcnt[kid];
-    if (m == 0) {
-      s.nwin[kid] = 0;
-      continue;
-    }
-    uint32_t* list = s.order + s.kaux[kid];
-    for (uint32_t i = 1; i < m; ++i) {  // insertion sort by pane
-      const uint32_t g = list[i];
-      const uint32_t p = (uint32_t)s.gid[g];
-      int j = (int)i - 1;
-      while (j >= 0 && (uint32_t)s.gid[list[j]] > p) {
-        list[j + 1] = list[j];
-        --j;
-      }
-      list[j + 1] = g;
-    }
-    s.nwin[kid] = sweep_windows(a, s, list, m, [](int64_t, uint32_t, uint32_t) {});
+  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {  // rank by pane within the key
+    const uint64_t gid = s.gid[g];
+    if (gid == kEmptyGid) continue;
+    const uint32_t kid = (uint32_t)(gid >> 32);
+    const uint32_t q = (uint32_t)gid;
+    const uint32_t ks = s.kaux[kid], m = s.kcnt[kid];
+    uint32_t r = 0;
+    for (uint32_t j = 0; j < m; ++j) r += (uint32_t)s.gid[s.order[ks + j]] < q;
+    s.sorted[ks + r] = ((uint64_t)q << 32) | (uint32_t)g;
   }
   __syncthreads();
-  const uint32_t total = block_scan_array<kAggTPB>(s.nwin, nk, s.scan);
+  // windows owned by each sorted entry -> order[i] (then exclusive offsets)
+  for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
+    const uint64_t v = s.sorted[i];
+    const int64_t q = (int64_t)(v >> 32);
+    const uint32_t kid = (uint32_t)(s.gid[(uint32_t)v] >> 32);
+    int64_t lo = first_win(q);
+    const int64_t hi = last_win(q);
+    if (i > s.kaux[kid]) lo = max(lo, last_win((int64_t)(s.sorted[i - 1] >> 32)) + 1);
+    s.order[i] = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
+  }
+  __syncthreads();
+  const uint32_t total = block_scan_array<kAggTPB>(s.order, (int)ng, s.scan);
   if (total == 0) return;
   const int64_t base = reserve_output(a, s, total);
   const int64_t wbase = b0 / a.R;
-  for (int kid = threadIdx.x; kid < nk; kid += kAggTPB) {
-    const uint32_t m = s.kcnt[kid];
-    if (m == 0) continue;
-    const uint32_t* list = s.order + s.kaux[kid];
-    const int64_t key = key_of(a, s, (uint32_t)kid);
-    int64_t idx = base + s.nwin[kid];
-    sweep_windows(a, s, list, m, [&](int64_t w, uint32_t jlo, uint32_t jhi) {
-      if (idx < a.cap) {
-        uint32_t cnt = 0;
-        for (uint32_t j = jlo; j <= jhi; ++j) cnt += s.gcnt[list[j]];
-        a.okey[idx] = key;
-        a.ows[idx] = a.origin + (w + wbase) * a.slide;
+  for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
+    const uint64_t v = s.sorted[i];
+    const int64_t q = (int64_t)(v >> 32);
+    const uint32_t kid = (uint32_t)(s.gid[(uint32_t)v] >> 32);
+    const uint32_t ks = s.kaux[kid], ke = ks + s.kcnt[kid];
+    int64_t lo = first_win(q);
+    const int64_t hi = last_win(q);
+    if (i > ks) lo = max(lo, last_win((int64_t)(s.sorted[i - 1] >> 32)) + 1);
+    const int64_t key = key_of(a, s, kid);
+    int64_t idx = base + s.order[i];
+    // The windows owned by entry i contain pane i and, as w grows, more of the
+    // key's later panes: their aggregates are extended incrementally.
+    uint32_t cnt = 0;
+    uint64_t acc[kMaxAggs];
 #pragma unroll
-        for (int k = 0; k < kMaxAggs; ++k) {
-          if (k < a.nagg) {
-            const int fn = a.afn[k];
-            if (fn == LMS_COUNT) {
-              ((int64_t*)a.oagg[k])[idx] = cnt;
-            } else {
-              const uint64_t* accs = s.acc + (size_t)a.aacc[k] * a.eg;
-              uint64_t v = acc_identity(fn);
-              for (uint32_t j = jlo; j <= jhi; ++j) v = combine(fn, v, accs[list[j]]);
-              if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)v) / (double)cnt;
-              else ((int64_t*)a.oagg[k])[idx] = (int64_t)v;
-            }
+    for (int k = 0; k < kMaxAggs; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
+    uint32_t jend = i;
+    for (int64_t w = lo; w <= hi; ++w, ++idx) {
+      while (jend < ke && first_win((int64_t)(s.sorted[jend] >> 32)) <= w) {
+        const uint32_t g = (uint32_t)s.sorted[jend];
+        cnt += s.gcnt[g];
+#pragma unroll
+        for (int k = 0; k < kMaxAggs; ++k)
+          if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + g]);
+        ++jend;
+      }
+      if (idx >= a.cap) continue;
+      a.okey[idx] = key;
+      a.ows[idx] = a.origin + (w + wbase) * a.slide;
+#pragma unroll
+      for (int k = 0; k < kMaxAggs; ++k) {
+        if (k < a.nagg) {
+          const int fn = a.afn[k];
+          if (fn == LMS_COUNT) {
+            ((int64_t*)a.oagg[k])[idx] = cnt;
+          } else {
+            const int slot = a.aacc[k];
+            uint64_t x = acc[0];
+#pragma unroll
+            for (int j = 1; j < kMaxAggs; ++j) x = slot == j ? acc[j] : x;
+            if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)x) / (double)cnt;
+            else ((int64_t*)a.oagg[k])[idx] = (int64_t)x;
           }
         }
       }
-      ++idx;
-    });
+    }
   }
 }
 
-// Segments of input elements: raw staged rows [lo, hi), or the partial records
-// written by the pieces of a split partition.
+// Input elements: raw staged rows [lo, hi), or the partial records that the
+// pieces of a split partition reserved in [lo, hi) of the partial arrays.
 struct Segments {
   bool partial;
-  uint32_t lo, hi;     // raw rows
-  uint32_t first, kp;  // partial: items first .. first+kp-1
+  uint32_t lo, hi;
 };
-
-__device__ __forceinline__ void seg_range(const WinArgs& a, const Segments& sg, uint32_t j, uint32_t& lo,
-                                          uint32_t& hi) {
-  if (!sg.partial) {
-    lo = sg.lo;
-    hi = sg.hi;
-  } else {
-    lo = a.items[sg.first + j].lo;
-    hi = lo + a.pcount[sg.first + j];
-  }
-}
 
 // Aggregates every element whose key hash lies in sub-ranges of [0, 2^32),
 // starting with the whole range and halving a range whenever its groups do not
 // fit the LDS tables, then composes and emits its windows.
 __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg) {
   const int64_t b0 = a.hdr[0];
-  const uint32_t nseg = sg.partial ? sg.kp : 1;
   if (threadIdx.x == 0) {
     s.stack[0] = 0;
     s.stack[1] = 1ull << 32;
@@ -698,21 +694,28 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg)
     clear_tables(a, s);
     __syncthreads();
     bool ovf = false;
-    for (uint32_t j = 0; j < nseg && !ovf; ++j) {
-      uint32_t lo, hi;
-      seg_range(a, sg, j, lo, hi);
+    {
+      const uint32_t lo = sg.lo, hi = sg.hi;
+      Elem cur;
+      if (lo + threadIdx.x < hi) {
+        if (sg.partial) load_partial(a, lo + threadIdx.x, cur);
+        else load_row(a, lo + threadIdx.x, cur);
+      }
       for (uint32_t b = lo; b < hi; b += kAggTPB) {
         const uint32_t e = b + threadIdx.x;
+        Elem nxt;  // the next round's element is loaded while this round inserts
+        if (e + kAggTPB < hi) {
+          if (sg.partial) load_partial(a, e + kAggTPB, nxt);
+          else load_row(a, e + kAggTPB, nxt);
+        }
         if (e < hi) {
-          Elem x;
-          if (sg.partial) load_partial(a, e, x);
-          else load_row(a, e, x);
-          const uint64_t h = fmix64((uint64_t)x.key);
+          const uint64_t h = fmix64((uint64_t)cur.key);
           const uint32_t sh = subhash(h);
           if (sh >= rlo && sh < rhi) {
-            if (!insert(a, s, x, h)) s.misc[M_OVF] = 1;
+            if (!insert(a, s, cur, h)) s.misc[M_OVF] = 1;
           }
         }
+        cur = nxt;
         __syncthreads();
         const bool o = s.misc[M_OVF] != 0;
         __syncthreads();  // every thread has read the flag before the next round may set it
@@ -746,9 +749,18 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg)
   }
 }
 
-// Writes the groups in the LDS tables as partial records at dst + pc.
-__device__ void flush_partials(const WinArgs& a, Lds& s, uint32_t dst) {
-  uint32_t run = s.misc[M_PC];
+// Writes the groups in the LDS tables as partial records into the partition's
+// partial region [start, ...), reserving their slots with one global atomic.
+__device__ void flush_partials(const WinArgs& a, Lds& s, const Item& it) {
+  uint32_t mine = 0;
+  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) mine += s.gid[g] != kEmptyGid;
+  const uint32_t total = block_sum<kAggTPB>(mine, s.scan);
+  if (total == 0) return;
+  if (threadIdx.x == 0) s.misc[M_PC] = a.pinfo[it.p].start + atomicAdd(&a.pfill[it.p], total);
+  __syncthreads();
+  const uint32_t dst = s.misc[M_PC];
+  __syncthreads();
+  uint32_t run = 0;
   for (int g0 = 0; g0 < a.eg; g0 += kAggTPB) {
     const int g = g0 + threadIdx.x;
     const bool occ = g < a.eg && s.gid[g] != kEmptyGid;
@@ -767,28 +779,25 @@ __device__ void flush_partials(const WinArgs& a, Lds& s, uint32_t dst) {
     run += rtot;
   }
   __syncthreads();
-  if (threadIdx.x == 0) s.misc[M_PC] = run;
-  __syncthreads();
 }
 
 // One piece of a split partition: aggregate its rows into partial records.
 // When a table fills up, the tables are flushed and the rows that did not fit
 // are inserted again into the emptied tables (at most one per thread, so they
 // always fit).
-__device__ void aggregate_piece(const WinArgs& a, Lds& s, uint32_t item, const Item& it) {
-  if (threadIdx.x == 0) {
-    s.misc[M_PC] = 0;
-    s.misc[M_OVF] = 0;
-  }
+__device__ void aggregate_piece(const WinArgs& a, Lds& s, const Item& it) {
+  if (threadIdx.x == 0) s.misc[M_OVF] = 0;
   clear_tables(a, s);
   __syncthreads();
+  Elem nxt;
+  if (it.lo + threadIdx.x < it.hi) load_row(a, it.lo + threadIdx.x, nxt);
   for (uint32_t b = it.lo; b < it.hi; b += kAggTPB) {
     const uint32_t e = b + threadIdx.x;
     bool pending = false;
-    Elem x;
+    Elem x = nxt;
+    if (e + kAggTPB < it.hi) load_row(a, e + kAggTPB, nxt);  // prefetch the next round
     uint64_t h = 0;
     if (e < it.hi) {
-      load_row(a, e, x);
       h = fmix64((uint64_t)x.key);
       if (!insert(a, s, x, h)) {
         pending = true;
@@ -799,7 +808,7 @@ __device__ void aggregate_piece(const WinArgs& a, Lds& s, uint32_t item, const I
     const bool o = s.misc[M_OVF] != 0;
     __syncthreads();
     if (o) {
-      flush_partials(a, s, it.lo);
+      flush_partials(a, s, it);
       clear_tables(a, s);
       if (threadIdx.x == 0) s.misc[M_OVF] = 0;
       __syncthreads();
@@ -807,8 +816,7 @@ __device__ void aggregate_piece(const WinArgs& a, Lds& s, uint32_t item, const I
       __syncthreads();
     }
   }
-  flush_partials(a, s, it.lo);
-  if (threadIdx.x == 0) a.pcount[item] = s.misc[M_PC];
+  flush_partials(a, s, it);
 }
 
 __global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
@@ -818,9 +826,9 @@ __global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
   Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
   const Item it = a.items[item];
   if (it.kp > 1) {
-    aggregate_piece(a, s, item, it);
+    aggregate_piece(a, s, it);
   } else {
-    Segments sg{false, it.lo, it.hi, 0, 0};
+    Segments sg{false, it.lo, it.hi};
     aggregate_and_emit(a, s, sg);
   }
 }
@@ -830,7 +838,7 @@ __global__ __launch_bounds__(kAggTPB) void k_wa_merge(WinArgs a) {
   if (pi.kp <= 1) return;
   extern __shared__ __align__(16) char lds_raw[];
   Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
-  Segments sg{true, 0, 0, pi.first, pi.kp};
+  Segments sg{true, pi.start, pi.start + a.pfill[blockIdx.x]};
   aggregate_and_emit(a, s, sg);
 }
 
@@ -899,7 +907,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   uint32_t* Rp = c.take<uint32_t>(p.nparts);
   PartInfo* pinfo = c.take<PartInfo>(p.nparts);
   Item* items = c.take<Item>(p.max_items);
-  uint32_t* pcount = c.take<uint32_t>(p.max_items);
+  uint32_t* pfill = c.take<uint32_t>(p.nparts);
   int64_t* skey = c.take<int64_t>(p.n);
   uint32_t* spane = c.take<uint32_t>(p.n);
   void* sval[kMaxAggs] = {};
@@ -916,7 +924,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
     a->Rp = Rp;
     a->pinfo = pinfo;
     a->items = items;
-    a->pcount = pcount;
+    a->pfill = pfill;
     a->skey = skey;
     a->spane = spane;
     for (int v = 0; v < kMaxAggs; ++v) a->sval[v] = sval[v];

@@ -20,7 +20,8 @@ from typing import Sequence
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblms.so")
+# LMS_LIB_PATH selects another build of the same ABI (e.g. an instrumented one)
+LIB_PATH = os.environ.get("LMS_LIB_PATH") or os.path.join(_HERE, "liblms.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2111_04289_amd.build`")
@@ -208,7 +209,7 @@ def _ws(workspace, nbytes, device):
 
 # ---- filter + project -------------------------------------------------------------
 
-def lms_filter_project(cols, preds=(), keep=(), projs=(), out=None, workspace=None, stream=None):
+def lms_filter_project(cols, preds=(), keep=(), projs=(), out=None, d_count=None, workspace=None, stream=None):
     """Enqueues filter+project; returns (out_cols, d_count) with out_cols sized n."""
     b = _Batch(cols)
     n = b.batch.nrows
@@ -222,7 +223,8 @@ def lms_filter_project(cols, preds=(), keep=(), projs=(), out=None, workspace=No
     pa, npred = _preds(preds)
     pr, nproj = _projs(projs)
     ka = (ctypes.c_int32 * max(1, len(keep)))(*keep)
-    d_count = torch.zeros(2, dtype=torch.int64, device=dev)
+    if d_count is None:
+        d_count = torch.zeros(2, dtype=torch.int64, device=dev)
     need = _lib.lms_filter_project_workspace(n)
     ws = _ws(workspace, need, dev)
     rc = _lib.lms_filter_project(ctypes.byref(b.batch), pa, npred, ka, len(keep), pr, nproj, ctypes.byref(ob.batch),

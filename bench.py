@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 23)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="time steps without per-kernel events")
+    ap.add_argument("--calib", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (scale reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -96,6 +98,14 @@ def main():
     if status != 0:
         log(f"window_agg device status {status}")
     log(f"counts {counts}")
+
+    if args.calib:
+        src = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # timed region: step events plus per-kernel events recorded by the library
     stream = torch.cuda.current_stream()

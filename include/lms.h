@@ -56,7 +56,7 @@ extern "C" {
 #define LMS_EHIP -2      /* a HIP runtime call or kernel launch failed */
 #define LMS_ENOMEM -3    /* workspace too small or a library allocation failed */
 #define LMS_ECAPACITY -4 /* device: a key has more distinct panes than one partition table holds */
-#define LMS_ERANGE -5    /* device: an event time lies more than 2^31 panes away from the batch's first row */
+#define LMS_ERANGE -5    /* device: an event time lies about 2^30 panes or more from the batch's first row */
 
 typedef void* lms_stream; /* hipStream_t */
 
@@ -166,7 +166,8 @@ int lms_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred
  * of which min(count, out->cap) are written.  d_count[1] is LMS_ECAPACITY if
  * a single key holds more distinct panes (pane = gcd(len, slide)) than one
  * workgroup table can hold (see lms_window_agg_pane_limit), LMS_ERANGE if an
- * event time is more than 2^31 panes away from the first row's.
+ * event time is 2^30 - slide/pane panes or more before, or 2^30 panes or more
+ * after, the first row's pane.
  * Workspace: lms_window_agg_workspace() with the same arguments. */
 size_t lms_window_agg_workspace(const lms_batch* in, int32_t key_col, const lms_window* w, const lms_agg* aggs,
                                 int32_t nagg);
@@ -199,6 +200,24 @@ size_t lms_hash_join_workspace(int64_t nprobe);
 int lms_hash_join(const lms_join_table* t, const lms_batch* probe, int32_t key_col, uint32_t* out_probe_idx,
                   int32_t* out_payload, int64_t cap, int64_t* d_count, void* workspace, size_t ws_bytes,
                   lms_stream stream);
+
+/* ---- CPU execution functions ---------------------------------------------
+ * The CPU side of MapDevice (Algorithm 2): the same operations on HOST
+ * columns (lms_col.data and every output pointer are host pointers), run
+ * synchronously on `nthreads` cores, the way an executor splits a micro-batch
+ * into NumCores partitions (Table I).  Semantics, dtypes and error codes are
+ * those of the GPU entry points above; `count` is a host int64 receiving the
+ * number of result rows (of which min(count, capacity) are written).  Window
+ * output rows come grouped by key partition, join pairs in probe order. */
+int lms_cpu_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred, const int32_t* keep,
+                           int32_t nkeep, const lms_proj* projs, int32_t nproj, const lms_batch* out, int64_t* count,
+                           int32_t nthreads);
+int lms_cpu_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs, int32_t nproj,
+                       int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg, const lms_groups* out,
+                       int64_t* count, int32_t nthreads);
+int lms_cpu_hash_join(const lms_batch* tbl, int32_t key_col, int32_t payload_col, const lms_batch* probe,
+                      int32_t probe_key_col, uint32_t* out_probe_idx, int32_t* out_payload, int64_t cap,
+                      int64_t* count, int32_t nthreads);
 
 /* ---- Kernel tracing ---------------------------------------------------------
  * Per-launch timing for profiling and for the timing records of the placement
@@ -245,9 +264,11 @@ typedef enum { LMS_DEV_CPU = 0, LMS_DEV_GPU = 1 } lms_device;
 typedef enum { LMS_PLAN_ANALYTIC = 0, LMS_PLAN_LEARNED = 1 } lms_plan_mode;
 
 typedef struct {
-  int32_t kind; /* lms_opkind */
-  int32_t reserved;
+  int32_t kind;     /* lms_opkind */
+  int32_t ncols;    /* columns the operation reads (learned mode) */
   double base_cost; /* <= 0: Table II default */
+  double window_s;  /* window length in seconds, 0 if not windowed (learned mode) */
+  double slide_s;   /* window slide in seconds, 0 = tumbling (learned mode) */
 } lms_op_desc;
 
 typedef struct {
@@ -257,6 +278,7 @@ typedef struct {
   int64_t rows;          /* rows of the micro-batch */
   double selectivity;    /* fraction of rows passing the filter */
   int64_t distinct_keys; /* estimated distinct group keys */
+  double interval_s;     /* seconds since the previous micro-batch */
 } lms_batch_stats;
 
 typedef struct {
@@ -264,12 +286,51 @@ typedef struct {
   double base_trans;  /* baseTransCost of Eq. 9 (initial 0.1) */
   int32_t mode;       /* lms_plan_mode */
   int32_t reserved;
-  const void* model; /* learned model for LMS_PLAN_LEARNED, else NULL */
+  const void* model; /* LMS_PLAN_LEARNED: a const lms_mlp_model*, else NULL */
 } lms_cost_params;
 
 double lms_table2_base_cost(int32_t kind);
 int lms_plan(const lms_op_desc* ops, int32_t nops, const lms_batch_stats* st, const lms_cost_params* cp,
              int32_t* out_dev, double* out_cost);
+
+/* ---- Learned placement model --------------------------------------------------
+ * A 12 -> 64 -> 64 -> 2 ReLU MLP predicting (log CPU ms, log GPU ms) of one
+ * operation; in LMS_PLAN_LEARNED mode lms_plan places each operation of the
+ * chain (Algorithm 2's walk) on the device with the smaller prediction, with
+ * Algorithm 2's transfer condition as an input feature instead of Eq. 9.
+ * Parameters (FP32, this order): W1[64][12], b1[64], W2[64][64], b2[64],
+ * W3[2][64], b3[2].  Features (lms_mlp_features):
+ *   x0 log2(rows+1)/24, x1 ncols/8, x2 selectivity, x3 log2(distinct+1)/20,
+ *   x4..x7 one-hot class {filter/project/scan, tumbling aggregation, sliding
+ *   aggregation, join}, x8 window_s/60, x9 slide_s/60, x10 interval_s/10,
+ *   x11 transfer flag (1 if the operation is first or last or follows a CPU
+ *   operation).
+ * Training (device, stream-ordered): lms_mlp_loss_grad computes the gradient
+ * of L = (1/n) sum_s sum_o mask[s][o] (y[s][o] - t[s][o])^2 over n samples
+ * (x: n x 12, t and mask: n x 2, row-major device arrays) into d_grad[NPARAMS]
+ * and d_loss[1]; lms_mlp_adam_step applies Adam.  lms_mlp_forward writes
+ * y (n x 2) with FP32 weights or, if use_bf16, weights rounded to BF16. */
+#define LMS_MLP_IN 12
+#define LMS_MLP_HIDDEN 64
+#define LMS_MLP_OUT 2
+#define LMS_MLP_NPARAMS (64 * 12 + 64 + 64 * 64 + 64 + 2 * 64 + 2)
+typedef struct lms_mlp lms_mlp;
+typedef struct {
+  float params[LMS_MLP_NPARAMS];
+} lms_mlp_model;
+int lms_mlp_create(uint64_t seed, lms_mlp** out);
+void lms_mlp_free(lms_mlp* m);
+int lms_mlp_set_params(lms_mlp* m, const float* host_params);
+int lms_mlp_get_params(const lms_mlp* m, float* host_params);
+size_t lms_mlp_workspace(int64_t n);
+int lms_mlp_loss_grad(const lms_mlp* m, const float* d_x, const float* d_t, const float* d_mask, int64_t n,
+                      float* d_grad, float* d_loss, void* workspace, size_t ws_bytes, lms_stream stream);
+int lms_mlp_adam_step(lms_mlp* m, const float* d_grad, float lr, float beta1, float beta2, float eps,
+                      lms_stream stream);
+int lms_mlp_forward(const lms_mlp* m, const float* d_x, int64_t n, float* d_y, int32_t use_bf16, lms_stream stream);
+void lms_mlp_host_forward(const float* host_params, const float* x, float* y);
+void lms_mlp_features(const lms_op_desc* op, const lms_batch_stats* st, int32_t transfer, float* x);
+float lms_bf16_round(float f);
 
 #ifdef __cplusplus
 }

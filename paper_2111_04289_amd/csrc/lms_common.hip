@@ -204,6 +204,7 @@ extern "C" int lms_plan(const lms_op_desc* ops, int32_t nops, const lms_batch_st
     if (!(b > 0)) return set_error(LMS_EINVAL, "operation %d has unknown kind %d", o, ops[o].kind);
   }
   if (cp->mode == LMS_PLAN_LEARNED && cp->model && plan_learned) {
+    for (int o = 0; o < nops; ++o) out_dev[o] = LMS_DEV_GPU;
     int rc = plan_learned(ops, nops, st, cp, out_dev, out_cost);
     if (rc == LMS_OK) return rc;
   }

@@ -14,7 +14,7 @@ namespace {
 
 constexpr int kTPB = 256;
 constexpr int kScanThreads = 1024;
-constexpr int kRows = 4;
+constexpr int kRows = 8;
 
 struct FpArgs {
   Query q;

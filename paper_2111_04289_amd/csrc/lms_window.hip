@@ -6,6 +6,8 @@
 // [origin + k*slide, origin + k*slide + len) that contains its event time.
 //
 // Method (MI355X-first; the paper delegates these operators to Spark-Rapids):
+//  * Pane indices are stored relative to a base 2^30 panes before the first
+//    row's pane, so they and the window indices fit 32 bits.
 //  * Pane decomposition replaces Expand: with pane = gcd(len, slide) every
 //    window is the union of len/pane consecutive panes, and each row falls in
 //    exactly one pane, so the row scan does one insertion per row instead of
@@ -36,6 +38,8 @@ constexpr uint64_t kEmptyGid = ~0ull;
 constexpr int kLdsLimit = 160 * 1024;
 constexpr int kStackCap = 80;
 constexpr int kUnroll = 4;
+constexpr int kHistUnroll = 8;
+constexpr int kXcds = 8;  // XCDs of an MI355X
 
 struct Item {
   uint32_t p, lo, hi, first;
@@ -118,7 +122,7 @@ __global__ void k_wa_init(WinArgs a) {
     if (a.q.nrows > 0) {
       const int64_t ts0 = load_i64(a.q.col[a.ts_col], a.q.dt[a.ts_col], 0);
       const int64_t q0 = floor_div(ts0 - a.origin, a.pane);
-      b0 = a.R * floor_div(q0 - (int64_t(1) << 31), a.R);
+      b0 = a.R * floor_div(q0 - (int64_t(1) << 30), a.R);
     }
     a.hdr[0] = b0;
   }
@@ -132,20 +136,20 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   const void* kc = a.q.col[a.key_col];
   const int kdt = a.q.dt[a.key_col];
-  // kUnroll rows per thread per step: all loads are issued before any use
-  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kUnroll) {
-    bool ok[kUnroll];
-    int64_t key[kUnroll];
-    int64_t idx[kUnroll];
+  // kHistUnroll rows per thread per step: all loads are issued before any use
+  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kHistUnroll) {
+    bool ok[kHistUnroll];
+    int64_t key[kHistUnroll];
+    int64_t idx[kHistUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kHistUnroll; ++u) {
       idx[u] = b + (int64_t)u * kScanTPB;
       ok[u] = idx[u] < hi;
       key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
     }
-    rows_pass<kUnroll>(a.q, idx, ok);
+    rows_pass<kHistUnroll>(a.q, idx, ok);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
+    for (int u = 0; u < kHistUnroll; ++u)
       if (ok[u]) atomicAdd(&hist[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
   }
   __syncthreads();
@@ -177,15 +181,26 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
   const uint32_t ibase = block_sum<kScanTPB>(s_items, scratch);
   const uint32_t rp = a.Rp[p];
   const uint32_t kp = (uint32_t)((rp + a.rs - 1) / a.rs);
-  // exclusive scan of H[p][*] over the chunks
-  const int per = (a.g1 + kScanTPB - 1) / kScanTPB;
-  const int w0 = threadIdx.x * per;
-  const int w1 = min(a.g1, w0 + per);
+  // exclusive scan of H[p][*] over the chunks, in XCD-major order: workgroups
+  // are dispatched round-robin over the 8 XCDs, so chunks w, w+8, w+16, ...
+  // run on one XCD at about the same time; placing their segments next to each
+  // other lets that XCD's L2 merge the partial lines they write.
+  const int c8 = (a.g1 + kXcds - 1) / kXcds;
+  const int nk = c8 * kXcds;
+  const int per = (nk + kScanTPB - 1) / kScanTPB;
+  const int k0 = threadIdx.x * per;
+  const int k1 = min(nk, k0 + per);
+  auto chunk_of = [&](int k) { return (k % c8) * kXcds + k / c8; };
   uint32_t loc = 0;
-  for (int w = w0; w < w1; ++w) loc += a.H[(size_t)p * a.g1 + w];
+  for (int k = k0; k < k1; ++k) {
+    const int w = chunk_of(k);
+    if (w < a.g1) loc += a.H[(size_t)p * a.g1 + w];
+  }
   uint32_t total;
   uint32_t run = start + block_excl_scan<kScanTPB>(loc, scratch, &total);
-  for (int w = w0; w < w1; ++w) {
+  for (int k = k0; k < k1; ++k) {
+    const int w = chunk_of(k);
+    if (w >= a.g1) continue;
     const uint32_t c = a.H[(size_t)p * a.g1 + w];
     a.Off[(size_t)p * a.g1 + w] = run;
     run += c;
@@ -224,6 +239,7 @@ __device__ __forceinline__ uint64_t staged_bits(const WinArgs& a, int v, int64_t
 // Scatter the passing rows, as (key, pane, value columns), to their partition.
 // Every column a row needs is loaded for all kUnroll rows of a thread before
 // the first LDS cursor atomic, so the loads overlap.
+template <int MA>
 __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
   extern __shared__ uint32_t cursor[];
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) cursor[p] = a.Off[(size_t)p * a.g1 + blockIdx.x];
@@ -239,7 +255,7 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
   for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kUnroll) {
     bool ok[kUnroll];
     int64_t key[kUnroll], ts[kUnroll], idx[kUnroll];
-    uint64_t val[kUnroll][kMaxAggs];
+    uint64_t val[kUnroll][MA];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       idx[u] = b + (int64_t)u * kScanTPB;
@@ -247,7 +263,7 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
       key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
       ts[u] = ok[u] ? load_i64(tc, tdt, idx[u]) : 0;
 #pragma unroll
-      for (int v = 0; v < kMaxAggs; ++v) val[u][v] = (ok[u] && v < a.nval) ? staged_bits(a, v, idx[u]) : 0;
+      for (int v = 0; v < MA; ++v) val[u][v] = (ok[u] && v < a.nval) ? staged_bits(a, v, idx[u]) : 0;
     }
     rows_pass<kUnroll>(a.q, idx, ok);
 #pragma unroll
@@ -258,14 +274,14 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
       uint64_t qp = 0;
       if (rel < 0) range_err = true;
       else qp = div_pane((uint64_t)rel, a.pane, a.inv_pane);
-      if (qp >= (1ull << 32)) {
+      if (qp >= (1ull << 31)) {
         range_err = true;
         qp = 0;
       }
       a.skey[pos] = key[u];
       a.spane[pos] = (uint32_t)qp;
 #pragma unroll
-      for (int v = 0; v < kMaxAggs; ++v) {
+      for (int v = 0; v < MA; ++v) {
         if (v < a.nval) {
           if (a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_F32) ((uint32_t*)a.sval[v])[pos] = (uint32_t)val[u][v];
           else ((uint64_t*)a.sval[v])[pos] = val[u][v];
@@ -287,6 +303,8 @@ struct Lds {
   uint32_t* gcnt;  // eg: rows per group
   uint32_t* order; // eg: group slots ordered by key, then windows per sorted entry
   uint64_t* sorted; // eg: (pane << 32 | group slot) in key-major, pane-sorted order
+  int32_t* fw;      // eg: first window containing the sorted entry's pane
+  int32_t* wlo;     // eg: first window owned by the sorted entry
   uint32_t* scan;  // kAggTPB / 64 + 1
   uint32_t* misc;  // flags and broadcasts
   uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
@@ -298,7 +316,7 @@ __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   size_t b = 0;
   b += align_up((size_t)(ek + 1) * 8, 16);
   b += 3 * align_up((size_t)(ek + 1) * 4, 16);
-  b += (size_t)eg * 8 + (size_t)nacc * eg * 8 + (size_t)eg * 4 + (size_t)eg * 4 + (size_t)eg * 8;
+  b += (size_t)eg * 8 + (size_t)nacc * eg * 8 + (size_t)eg * 4 + (size_t)eg * 4 + (size_t)eg * 8 + (size_t)eg * 8;
   b += align_up((kAggTPB / 64 + 1) * 4, 16) + M_WORDS * 4;
   b += 2 * kStackCap * 8;
   return b;
@@ -325,6 +343,10 @@ __device__ __forceinline__ Lds carve_lds(char* base, int ek, int eg, int nacc) {
   o += (size_t)eg * 4;
   s.sorted = (uint64_t*)(base + o);
   o += (size_t)eg * 8;
+  s.fw = (int32_t*)(base + o);
+  o += (size_t)eg * 4;
+  s.wlo = (int32_t*)(base + o);
+  o += (size_t)eg * 4;
   s.scan = (uint32_t*)(base + o);
   o += align_up((kAggTPB / 64 + 1) * 4, 16);
   s.misc = (uint32_t*)(base + o);
@@ -349,6 +371,7 @@ __device__ __forceinline__ uint64_t combine(int fn, uint64_t x, uint64_t y) {
   }
 }
 
+template <int MA>
 __device__ void clear_tables(const WinArgs& a, Lds& s) {
   for (int i = threadIdx.x; i <= a.ek; i += kAggTPB) {
     s.keys[i] = kEmptyKey;
@@ -361,7 +384,7 @@ __device__ void clear_tables(const WinArgs& a, Lds& s) {
     s.gcnt[g] = 0;
   }
 #pragma unroll
-  for (int k = 0; k < kMaxAggs; ++k) {
+  for (int k = 0; k < MA; ++k) {
     if (k < a.nacc) {
       const uint64_t id = acc_identity(a.accfn[k]);
       for (int g = threadIdx.x; g < a.eg; g += kAggTPB) s.acc[(size_t)k * a.eg + g] = id;
@@ -371,20 +394,22 @@ __device__ void clear_tables(const WinArgs& a, Lds& s) {
 
 // One input element: a staged row (cnt 1) or a partial record.  Only ever
 // indexed with compile-time indices, so it lives in registers.
+template <int MA>
 struct Elem {
   int64_t key;
   uint32_t pane;
   uint32_t cnt;
-  uint64_t in[kMaxAggs];  // input of accumulator k (int64 or double bits)
+  uint64_t in[MA];  // input of accumulator k (int64 or double bits)
 };
 
-__device__ __forceinline__ void load_row(const WinArgs& a, uint32_t e, Elem& x) {
+template <int MA>
+__device__ __forceinline__ void load_row(const WinArgs& a, uint32_t e, Elem<MA>& x) {
   x.key = a.skey[e];
   x.pane = a.spane[e];
   x.cnt = 1;
-  uint64_t raw[kMaxAggs];  // staged value v: int64, or double bits for float columns
+  uint64_t raw[MA];  // staged value v: int64, or double bits for float columns
 #pragma unroll
-  for (int v = 0; v < kMaxAggs; ++v) {
+  for (int v = 0; v < MA; ++v) {
     raw[v] = 0;
     if (v < a.nval) {
       const void* c = a.sval[v];
@@ -397,25 +422,26 @@ __device__ __forceinline__ void load_row(const WinArgs& a, uint32_t e, Elem& x) 
     }
   }
 #pragma unroll
-  for (int k = 0; k < kMaxAggs; ++k) {
+  for (int k = 0; k < MA; ++k) {
     x.in[k] = 0;
     if (k < a.nacc) {
       const int v = a.accval[k];
       uint64_t r = raw[0];
 #pragma unroll
-      for (int j = 1; j < kMaxAggs; ++j) r = v == j ? raw[j] : r;
+      for (int j = 1; j < MA; ++j) r = v == j ? raw[j] : r;
       const bool is_int = a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_I64;
       x.in[k] = (a.accfn[k] == LMS_AVG && is_int) ? (uint64_t)__double_as_longlong((double)(int64_t)r) : r;
     }
   }
 }
 
-__device__ __forceinline__ void load_partial(const WinArgs& a, uint32_t e, Elem& x) {
+template <int MA>
+__device__ __forceinline__ void load_partial(const WinArgs& a, uint32_t e, Elem<MA>& x) {
   x.key = a.pkey[e];
   x.pane = a.ppane[e];
   x.cnt = a.pcnt[e];
 #pragma unroll
-  for (int k = 0; k < kMaxAggs; ++k) x.in[k] = k < a.nacc ? a.pacc[k][e] : 0;
+  for (int k = 0; k < MA; ++k) x.in[k] = k < a.nacc ? a.pacc[k][e] : 0;
 }
 
 __device__ __forceinline__ uint32_t group_hash(uint64_t gid) {
@@ -427,7 +453,8 @@ __device__ __forceinline__ uint32_t group_hash(uint64_t gid) {
 }
 
 // Inserts one element; returns false if a table is full.
-__device__ __forceinline__ bool insert(const WinArgs& a, Lds& s, const Elem& x, uint64_t h) {
+template <int MA>
+__device__ __forceinline__ bool insert(const WinArgs& a, Lds& s, const Elem<MA>& x, uint64_t h) {
   int kid;
   if ((uint64_t)x.key == kEmptyKey) {
     kid = a.ek;
@@ -475,7 +502,7 @@ __device__ __forceinline__ bool insert(const WinArgs& a, Lds& s, const Elem& x, 
   if (g < 0) return false;
   atomicAdd(&s.gcnt[g], x.cnt);
 #pragma unroll
-  for (int k = 0; k < kMaxAggs; ++k) {
+  for (int k = 0; k < MA; ++k) {
     if (k < a.nacc) {
       uint64_t* p = s.acc + (size_t)k * a.eg + g;
       switch (a.accfn[k]) {
@@ -507,6 +534,7 @@ __device__ int64_t reserve_output(const WinArgs& a, Lds& s, uint32_t total) {
 }
 
 // Tumbling windows: every group (key, pane) is one output row.
+template <int MA>
 __device__ void emit_tumbling(const WinArgs& a, Lds& s, int64_t b0) {
   uint32_t mine = 0;
   for (int g = threadIdx.x; g < a.eg; g += kAggTPB) mine += s.gid[g] != kEmptyGid;
@@ -527,7 +555,7 @@ __device__ void emit_tumbling(const WinArgs& a, Lds& s, int64_t b0) {
         a.okey[idx] = key_of(a, s, (uint32_t)(gid >> 32));
         a.ows[idx] = a.origin + (b0 + (int64_t)(uint32_t)gid) * a.len;
 #pragma unroll
-        for (int k = 0; k < kMaxAggs; ++k) {
+        for (int k = 0; k < MA; ++k) {
           if (k < a.nagg) {
             const int fn = a.afn[k];
             if (fn == LMS_COUNT) {
@@ -565,8 +593,11 @@ __device__ __forceinline__ int64_t fdiv(int64_t x, int64_t d, double inv) {
 // per pane) into key-major, pane-sorted order.  Each window of a key is
 // produced by the first of the key's panes it contains: pane i covers windows
 // first_win(q_i)..last_win(q_i), of which it owns those after the previous
-// pane's last window.  A window's panes are then that owner and the following
-// panes of the key whose first window is not later than it.
+// pane's last window.  Output rows are then produced one per thread, so
+// consecutive threads write consecutive rows: row r belongs to the last entry
+// whose owned windows start at or before r, and its window holds that entry's
+// pane and the key's following panes whose first window is not later.
+template <int MA>
 __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   const int nk = a.ek + 1;
   auto first_win = [&](int64_t q) { return fdiv(q - a.W, a.R, a.inv_R) + 1; };
@@ -588,75 +619,80 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
     }
   }
   __syncthreads();
+  int32_t* const wpane = s.wlo;  // panes of the unsorted key runs, only while ranking
+  for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) wpane[i] = (int32_t)(uint32_t)s.gid[s.order[i]];
+  __syncthreads();
   for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {  // rank by pane within the key
     const uint64_t gid = s.gid[g];
     if (gid == kEmptyGid) continue;
     const uint32_t kid = (uint32_t)(gid >> 32);
-    const uint32_t q = (uint32_t)gid;
+    const int32_t q = (int32_t)(uint32_t)gid;
     const uint32_t ks = s.kaux[kid], m = s.kcnt[kid];
-    uint32_t r = 0;
-    for (uint32_t j = 0; j < m; ++j) r += (uint32_t)s.gid[s.order[ks + j]] < q;
-    s.sorted[ks + r] = ((uint64_t)q << 32) | (uint32_t)g;
+    uint32_t r = 0, j = 0;
+    for (; j + 8 <= m; j += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) r += wpane[ks + j + u] < q;
+    }
+    for (; j < m; ++j) r += wpane[ks + j] < q;
+    s.sorted[ks + r] = ((uint64_t)(uint32_t)q << 32) | (uint32_t)g;
   }
   __syncthreads();
-  // windows owned by each sorted entry -> order[i] (then exclusive offsets)
   for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
     const uint64_t v = s.sorted[i];
     const int64_t q = (int64_t)(v >> 32);
     const uint32_t kid = (uint32_t)(s.gid[(uint32_t)v] >> 32);
-    int64_t lo = first_win(q);
+    const int64_t fw = first_win(q);
     const int64_t hi = last_win(q);
+    int64_t lo = fw;
     if (i > s.kaux[kid]) lo = max(lo, last_win((int64_t)(s.sorted[i - 1] >> 32)) + 1);
+    s.fw[i] = (int32_t)fw;
+    s.wlo[i] = (int32_t)lo;
     s.order[i] = hi >= lo ? (uint32_t)(hi - lo + 1) : 0u;
   }
   __syncthreads();
-  const uint32_t total = block_scan_array<kAggTPB>(s.order, (int)ng, s.scan);
+  const uint32_t total = block_scan_array<kAggTPB>(s.order, (int)ng, s.scan);  // order = first row of entry
   if (total == 0) return;
   const int64_t base = reserve_output(a, s, total);
   const int64_t wbase = b0 / a.R;
-  for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
-    const uint64_t v = s.sorted[i];
-    const int64_t q = (int64_t)(v >> 32);
-    const uint32_t kid = (uint32_t)(s.gid[(uint32_t)v] >> 32);
-    const uint32_t ks = s.kaux[kid], ke = ks + s.kcnt[kid];
-    int64_t lo = first_win(q);
-    const int64_t hi = last_win(q);
-    if (i > ks) lo = max(lo, last_win((int64_t)(s.sorted[i - 1] >> 32)) + 1);
-    const int64_t key = key_of(a, s, kid);
-    int64_t idx = base + s.order[i];
-    // The windows owned by entry i contain pane i and, as w grows, more of the
-    // key's later panes: their aggregates are extended incrementally.
+  for (uint32_t r = threadIdx.x; r < total; r += kAggTPB) {
+    uint32_t lo = 0, hi = ng - 1;  // last entry i with order[i] <= r
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi + 1) >> 1;
+      if (s.order[mid] <= r) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t i = lo;
+    const int64_t idx = base + r;
+    if (idx >= a.cap) continue;
+    const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
+    const uint32_t kid = (uint32_t)(s.gid[(uint32_t)s.sorted[i]] >> 32);
+    const uint32_t ke = s.kaux[kid] + s.kcnt[kid];
     uint32_t cnt = 0;
-    uint64_t acc[kMaxAggs];
+    uint64_t acc[MA];
 #pragma unroll
-    for (int k = 0; k < kMaxAggs; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
-    uint32_t jend = i;
-    for (int64_t w = lo; w <= hi; ++w, ++idx) {
-      while (jend < ke && first_win((int64_t)(s.sorted[jend] >> 32)) <= w) {
-        const uint32_t g = (uint32_t)s.sorted[jend];
-        cnt += s.gcnt[g];
+    for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
+    for (uint32_t j = i; j < ke && s.fw[j] <= w; ++j) {
+      const uint32_t g = (uint32_t)s.sorted[j];
+      cnt += s.gcnt[g];
 #pragma unroll
-        for (int k = 0; k < kMaxAggs; ++k)
-          if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + g]);
-        ++jend;
-      }
-      if (idx >= a.cap) continue;
-      a.okey[idx] = key;
-      a.ows[idx] = a.origin + (w + wbase) * a.slide;
+      for (int k = 0; k < MA; ++k)
+        if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + g]);
+    }
+    a.okey[idx] = key_of(a, s, kid);
+    a.ows[idx] = a.origin + ((int64_t)w + wbase) * a.slide;
 #pragma unroll
-      for (int k = 0; k < kMaxAggs; ++k) {
-        if (k < a.nagg) {
-          const int fn = a.afn[k];
-          if (fn == LMS_COUNT) {
-            ((int64_t*)a.oagg[k])[idx] = cnt;
-          } else {
-            const int slot = a.aacc[k];
-            uint64_t x = acc[0];
+    for (int k = 0; k < MA; ++k) {
+      if (k < a.nagg) {
+        const int fn = a.afn[k];
+        if (fn == LMS_COUNT) {
+          ((int64_t*)a.oagg[k])[idx] = cnt;
+        } else {
+          const int slot = a.aacc[k];
+          uint64_t x = acc[0];
 #pragma unroll
-            for (int j = 1; j < kMaxAggs; ++j) x = slot == j ? acc[j] : x;
-            if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)x) / (double)cnt;
-            else ((int64_t*)a.oagg[k])[idx] = (int64_t)x;
-          }
+          for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
+          if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)x) / (double)cnt;
+          else ((int64_t*)a.oagg[k])[idx] = (int64_t)x;
         }
       }
     }
@@ -673,6 +709,7 @@ struct Segments {
 // Aggregates every element whose key hash lies in sub-ranges of [0, 2^32),
 // starting with the whole range and halving a range whenever its groups do not
 // fit the LDS tables, then composes and emits its windows.
+template <int MA>
 __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg) {
   const int64_t b0 = a.hdr[0];
   if (threadIdx.x == 0) {
@@ -691,28 +728,28 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg)
       s.misc[M_SSIZE] = ssize - 1;
       s.misc[M_OVF] = 0;
     }
-    clear_tables(a, s);
+    clear_tables<MA>(a, s);
     __syncthreads();
     bool ovf = false;
     {
       const uint32_t lo = sg.lo, hi = sg.hi;
-      Elem cur;
+      Elem<MA> cur;
       if (lo + threadIdx.x < hi) {
-        if (sg.partial) load_partial(a, lo + threadIdx.x, cur);
-        else load_row(a, lo + threadIdx.x, cur);
+        if (sg.partial) load_partial<MA>(a, lo + threadIdx.x, cur);
+        else load_row<MA>(a, lo + threadIdx.x, cur);
       }
       for (uint32_t b = lo; b < hi; b += kAggTPB) {
         const uint32_t e = b + threadIdx.x;
-        Elem nxt;  // the next round's element is loaded while this round inserts
+        Elem<MA> nxt;  // the next round's element is loaded while this round inserts
         if (e + kAggTPB < hi) {
-          if (sg.partial) load_partial(a, e + kAggTPB, nxt);
-          else load_row(a, e + kAggTPB, nxt);
+          if (sg.partial) load_partial<MA>(a, e + kAggTPB, nxt);
+          else load_row<MA>(a, e + kAggTPB, nxt);
         }
         if (e < hi) {
           const uint64_t h = fmix64((uint64_t)cur.key);
           const uint32_t sh = subhash(h);
           if (sh >= rlo && sh < rhi) {
-            if (!insert(a, s, cur, h)) s.misc[M_OVF] = 1;
+            if (!insert<MA>(a, s, cur, h)) s.misc[M_OVF] = 1;
           }
         }
         cur = nxt;
@@ -743,14 +780,15 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg)
       __syncthreads();
       continue;
     }
-    if (a.R == 1 && a.W == 1) emit_tumbling(a, s, b0);
-    else emit_sliding(a, s, b0);
+    if (a.R == 1 && a.W == 1) emit_tumbling<MA>(a, s, b0);
+    else emit_sliding<MA>(a, s, b0);
     __syncthreads();
   }
 }
 
 // Writes the groups in the LDS tables as partial records into the partition's
 // partial region [start, ...), reserving their slots with one global atomic.
+template <int MA>
 __device__ void flush_partials(const WinArgs& a, Lds& s, const Item& it) {
   uint32_t mine = 0;
   for (int g = threadIdx.x; g < a.eg; g += kAggTPB) mine += s.gid[g] != kEmptyGid;
@@ -773,7 +811,7 @@ __device__ void flush_partials(const WinArgs& a, Lds& s, const Item& it) {
       a.ppane[e] = (uint32_t)gid;
       a.pcnt[e] = s.gcnt[g];
 #pragma unroll
-      for (int k = 0; k < kMaxAggs; ++k)
+      for (int k = 0; k < MA; ++k)
         if (k < a.nacc) a.pacc[k][e] = s.acc[(size_t)k * a.eg + g];
     }
     run += rtot;
@@ -785,21 +823,22 @@ __device__ void flush_partials(const WinArgs& a, Lds& s, const Item& it) {
 // When a table fills up, the tables are flushed and the rows that did not fit
 // are inserted again into the emptied tables (at most one per thread, so they
 // always fit).
+template <int MA>
 __device__ void aggregate_piece(const WinArgs& a, Lds& s, const Item& it) {
   if (threadIdx.x == 0) s.misc[M_OVF] = 0;
-  clear_tables(a, s);
+  clear_tables<MA>(a, s);
   __syncthreads();
-  Elem nxt;
-  if (it.lo + threadIdx.x < it.hi) load_row(a, it.lo + threadIdx.x, nxt);
+  Elem<MA> nxt;
+  if (it.lo + threadIdx.x < it.hi) load_row<MA>(a, it.lo + threadIdx.x, nxt);
   for (uint32_t b = it.lo; b < it.hi; b += kAggTPB) {
     const uint32_t e = b + threadIdx.x;
     bool pending = false;
-    Elem x = nxt;
-    if (e + kAggTPB < it.hi) load_row(a, e + kAggTPB, nxt);  // prefetch the next round
+    Elem<MA> x = nxt;
+    if (e + kAggTPB < it.hi) load_row<MA>(a, e + kAggTPB, nxt);  // prefetch the next round
     uint64_t h = 0;
     if (e < it.hi) {
       h = fmix64((uint64_t)x.key);
-      if (!insert(a, s, x, h)) {
+      if (!insert<MA>(a, s, x, h)) {
         pending = true;
         s.misc[M_OVF] = 1;
       }
@@ -808,17 +847,18 @@ __device__ void aggregate_piece(const WinArgs& a, Lds& s, const Item& it) {
     const bool o = s.misc[M_OVF] != 0;
     __syncthreads();
     if (o) {
-      flush_partials(a, s, it);
-      clear_tables(a, s);
+      flush_partials<MA>(a, s, it);
+      clear_tables<MA>(a, s);
       if (threadIdx.x == 0) s.misc[M_OVF] = 0;
       __syncthreads();
-      if (pending) insert(a, s, x, h);
+      if (pending) insert<MA>(a, s, x, h);
       __syncthreads();
     }
   }
-  flush_partials(a, s, it);
+  flush_partials<MA>(a, s, it);
 }
 
+template <int MA>
 __global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
   const uint32_t item = blockIdx.x;
   if ((int64_t)item >= a.hdr[1]) return;
@@ -826,20 +866,21 @@ __global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
   Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
   const Item it = a.items[item];
   if (it.kp > 1) {
-    aggregate_piece(a, s, it);
+    aggregate_piece<MA>(a, s, it);
   } else {
     Segments sg{false, it.lo, it.hi};
-    aggregate_and_emit(a, s, sg);
+    aggregate_and_emit<MA>(a, s, sg);
   }
 }
 
+template <int MA>
 __global__ __launch_bounds__(kAggTPB) void k_wa_merge(WinArgs a) {
   const PartInfo pi = a.pinfo[blockIdx.x];
   if (pi.kp <= 1) return;
   extern __shared__ __align__(16) char lds_raw[];
   Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
   Segments sg{true, pi.start, pi.start + a.pfill[blockIdx.x]};
-  aggregate_and_emit(a, s, sg);
+  aggregate_and_emit<MA>(a, s, sg);
 }
 
 // ---- host planning -------------------------------------------------------------
@@ -988,6 +1029,19 @@ int validate_window(const lms_batch* in, int32_t key_col, const lms_window* w) {
   return LMS_OK;
 }
 
+template <int MA>
+void launch_tail(const Plan& p, const WinArgs& a, size_t plds, hipStream_t st) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)k_wa_agg<MA>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+    (void)hipFuncSetAttribute((const void*)k_wa_merge<MA>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
+    attr_done = true;
+  }
+  LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(p.g1), dim3(kScanTPB), plds, st, a);
+  LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(p.max_items), dim3(kAggTPB), p.lds, st, a);
+  LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(p.nparts), dim3(kAggTPB), p.lds, st, a);
+}
+
 }  // namespace
 }  // namespace lms
 
@@ -1068,21 +1122,17 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
   a.d_count = d_count;
 
   hipStream_t st = (hipStream_t)stream;
-  static bool attr_done = false;
-  if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)k_wa_agg, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
-    (void)hipFuncSetAttribute((const void*)k_wa_merge, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
-    attr_done = true;
-  }
   LMS_LAUNCH("k_wa_init", k_wa_init, dim3(1), dim3(64), 0, st, a);
   if (in->nrows > 0) {
     const size_t plds = (size_t)p.nparts * 4;
     LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(p.g1), dim3(kScanTPB), plds, st, a);
     LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
-    LMS_LAUNCH("k_wa_scatter", k_wa_scatter, dim3(p.g1), dim3(kScanTPB), plds, st, a);
-    LMS_LAUNCH("k_wa_agg", k_wa_agg, dim3(p.max_items), dim3(kAggTPB), p.lds, st, a);
-    LMS_LAUNCH("k_wa_merge", k_wa_merge, dim3(p.nparts), dim3(kAggTPB), p.lds, st, a);
+    // loops over aggregates are unrolled to the smallest bound covering nagg
+    if (nagg <= 2) launch_tail<2>(p, a, plds, st);
+    else if (nagg <= 4) launch_tail<4>(p, a, plds, st);
+    else if (nagg <= 6) launch_tail<6>(p, a, plds, st);
+    else launch_tail<8>(p, a, plds, st);
   }
   return check_hip(hipGetLastError(), "window_agg launch");
 }

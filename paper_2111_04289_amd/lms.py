@@ -80,12 +80,14 @@ class lms_groups(ctypes.Structure):
 
 
 class lms_op_desc(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("base_cost", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int32), ("ncols", ctypes.c_int32), ("base_cost", ctypes.c_double),
+                ("window_s", ctypes.c_double), ("slide_s", ctypes.c_double)]
 
 
 class lms_batch_stats(ctypes.Structure):
     _fields_ = [("batch_bytes", ctypes.c_int64), ("num_cores", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("rows", ctypes.c_int64), ("selectivity", ctypes.c_double), ("distinct_keys", ctypes.c_int64)]
+                ("rows", ctypes.c_int64), ("selectivity", ctypes.c_double), ("distinct_keys", ctypes.c_int64),
+                ("interval_s", ctypes.c_double)]
 
 
 class lms_cost_params(ctypes.Structure):
@@ -116,6 +118,24 @@ _SIGS = {
     "lms_join_free": (None, [_vp]),
     "lms_hash_join_workspace": (_sz, [_i64]),
     "lms_hash_join": (ctypes.c_int, [_vp, _P(lms_batch), _i32, _vp, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "lms_cpu_filter_project": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(ctypes.c_int32), _i32,
+                                              _P(lms_proj), _i32, _P(lms_batch), _P(ctypes.c_int64), _i32]),
+    "lms_cpu_window_agg": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _i32,
+                                          _P(lms_window), _P(lms_agg), _i32, _P(lms_groups), _P(ctypes.c_int64), _i32]),
+    "lms_cpu_hash_join": (ctypes.c_int, [_P(lms_batch), _i32, _i32, _P(lms_batch), _i32, _vp, _vp, _i64,
+                                         _P(ctypes.c_int64), _i32]),
+    "lms_mlp_create": (ctypes.c_int, [ctypes.c_uint64, _P(_vp)]),
+    "lms_mlp_free": (None, [_vp]),
+    "lms_mlp_set_params": (ctypes.c_int, [_vp, _vp]),
+    "lms_mlp_get_params": (ctypes.c_int, [_vp, _vp]),
+    "lms_mlp_workspace": (_sz, [_i64]),
+    "lms_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "lms_mlp_adam_step": (ctypes.c_int, [_vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                         _vp]),
+    "lms_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i32, _vp]),
+    "lms_mlp_host_forward": (None, [_vp, _vp, _vp]),
+    "lms_mlp_features": (None, [_P(lms_op_desc), _P(lms_batch_stats), _i32, _vp]),
+    "lms_bf16_round": (ctypes.c_float, [ctypes.c_float]),
     "lms_trace_enable": (ctypes.c_int, [_i32]),
     "lms_trace_read": (ctypes.c_int, [_P(lms_trace_stat), _i32]),
     "lms_table2_base_cost": (ctypes.c_double, [_i32]),
@@ -351,6 +371,59 @@ def lms_hash_join(table: JoinTable, probe_keys: torch.Tensor, cap: int | None = 
     return out[0], out[1], d_count
 
 
+# ---- CPU execution functions (host tensors, synchronous) -------------------------------------
+
+def lms_cpu_filter_project(cols, preds=(), keep=(), projs=(), nthreads=1):
+    """Filter + project on host tensors; returns the trimmed output columns."""
+    b = _Batch(cols)
+    n = b.batch.nrows
+    keep, projs = list(keep), list(projs)
+    out = [torch.empty(n, dtype=cols[c].dtype) for c in keep] + [torch.empty(n, dtype=cols[p[0]].dtype) for p in projs]
+    ob = _Batch(out, nrows=n)
+    pa, npred = _preds(preds)
+    pr, nproj = _projs(projs)
+    ka = (ctypes.c_int32 * max(1, len(keep)))(*keep)
+    cnt = ctypes.c_int64(0)
+    _check(_lib.lms_cpu_filter_project(ctypes.byref(b.batch), pa, npred, ka, len(keep), pr, nproj,
+                                       ctypes.byref(ob.batch), ctypes.byref(cnt), nthreads))
+    return [o[:cnt.value] for o in out]
+
+
+def lms_cpu_window_agg(cols, key_col, window: "Window", aggs, preds=(), projs=(), cap=None, nthreads=1):
+    """Windowed group-by on host tensors; returns (key, wstart, [aggs]) trimmed to the group count."""
+    b = _Batch(cols)
+    n = b.batch.nrows
+    aggs = list(aggs)
+    if cap is None:
+        slide = window.slide or window.length
+        cap = n * (-(-window.length // slide))
+    g = Groups(cap, aggs, torch.device("cpu"))
+    pa, npred = _preds(preds)
+    pr, nproj = _projs(projs)
+    aa = (lms_agg * max(1, len(aggs)))(*[lms_agg(f, c) for f, c in aggs])
+    w = window.c()
+    cnt = ctypes.c_int64(0)
+    _check(_lib.lms_cpu_window_agg(ctypes.byref(b.batch), pa, npred, pr, nproj, key_col, ctypes.byref(w), aa,
+                                   len(aggs), ctypes.byref(g.c), ctypes.byref(cnt), nthreads))
+    m = min(cnt.value, cap)
+    return g.key[:m], g.wstart[:m], [a[:m] for a in g.aggs], cnt.value
+
+
+def lms_cpu_hash_join(build_keys, build_payload, probe_keys, cap=None, nthreads=1):
+    """Join on host tensors; returns (probe_idx int32 view of uint32, payload, count)."""
+    tb = _Batch([build_keys, build_payload])
+    pb = _Batch([probe_keys])
+    if cap is None:
+        cap = max(1, int(probe_keys.shape[0]) * 4)
+    oi = torch.empty(cap, dtype=torch.int32)
+    op = torch.empty(cap, dtype=torch.int32)
+    cnt = ctypes.c_int64(0)
+    _check(_lib.lms_cpu_hash_join(ctypes.byref(tb.batch), 0, 1, ctypes.byref(pb.batch), 0, oi.data_ptr(),
+                                  op.data_ptr(), cap, ctypes.byref(cnt), nthreads))
+    m = min(cnt.value, cap)
+    return oi[:m], op[:m], cnt.value
+
+
 # ---- kernel tracing ----------------------------------------------------------------------
 
 def lms_trace_enable(on: bool = True):
@@ -374,16 +447,102 @@ def table2_base_cost(kind: int) -> float:
 
 
 def lms_plan(kinds, batch_bytes, num_cores, infpt_bytes=150.0 * 1024, base_trans=0.1, base_costs=None,
-             rows=0, selectivity=1.0, distinct_keys=0, mode=PLAN_ANALYTIC, model=None):
-    """MapDevice (Algorithm 2) over the chain `kinds`; returns (devices, costs)."""
+             rows=0, selectivity=1.0, distinct_keys=0, mode=PLAN_ANALYTIC, model=None, ncols=None, window_s=None,
+             slide_s=None, interval_s=0.0):
+    """MapDevice (Algorithm 2) over the chain `kinds`; returns (devices, costs).
+
+    model: float32 array of the MLP's parameters (LMS_PLAN_LEARNED mode)."""
     kinds = list(kinds)
     n = len(kinds)
     ops = (lms_op_desc * max(1, n))()
     for i, k in enumerate(kinds):
-        ops[i] = lms_op_desc(k, 0, float(base_costs[i]) if base_costs is not None else 0.0)
-    st = lms_batch_stats(int(batch_bytes), int(num_cores), 0, int(rows), float(selectivity), int(distinct_keys))
-    cp = lms_cost_params(float(infpt_bytes), float(base_trans), mode, 0, model)
+        ops[i] = lms_op_desc(k, int(ncols[i]) if ncols is not None else 1,
+                             float(base_costs[i]) if base_costs is not None else 0.0,
+                             float(window_s[i]) if window_s is not None else 0.0,
+                             float(slide_s[i]) if slide_s is not None else 0.0)
+    st = lms_batch_stats(int(batch_bytes), int(num_cores), 0, int(rows), float(selectivity), int(distinct_keys),
+                         float(interval_s))
+    keep = None
+    mp = None
+    if model is not None:
+        import numpy as np
+        keep = np.ascontiguousarray(model, dtype=np.float32)
+        if keep.size != MLP_NPARAMS:
+            raise ValueError("model must hold MLP_NPARAMS float32 parameters")
+        mp = keep.ctypes.data
+    cp = lms_cost_params(float(infpt_bytes), float(base_trans), mode, 0, mp)
     dev = (ctypes.c_int32 * max(1, n))()
     cost = (ctypes.c_double * max(1, n))()
     _check(_lib.lms_plan(ops, n, ctypes.byref(st), ctypes.byref(cp), dev, cost))
     return list(dev)[:n], list(cost)[:n]
+
+
+# ---- learned placement model -------------------------------------------------------------
+
+MLP_NPARAMS = 64 * 12 + 64 + 64 * 64 + 64 + 2 * 64 + 2
+
+
+def mlp_features(kind, rows, ncols, selectivity, distinct_keys, window_s, slide_s, interval_s, transfer):
+    """The model's 12 input features of one operation (the library's definition)."""
+    import numpy as np
+    op = lms_op_desc(kind, int(ncols), 0.0, float(window_s), float(slide_s))
+    st = lms_batch_stats(0, 1, 0, int(rows), float(selectivity), int(distinct_keys), float(interval_s))
+    x = np.zeros(12, np.float32)
+    _lib.lms_mlp_features(ctypes.byref(op), ctypes.byref(st), int(transfer), x.ctypes.data)
+    return x
+
+
+class Mlp:
+    """Device copy of the placement MLP with its Adam state."""
+
+    def __init__(self, seed: int = 0, device=None):
+        self.device = device or torch.device("cuda")
+        h = ctypes.c_void_p(0)
+        _check(_lib.lms_mlp_create(int(seed), ctypes.byref(h)))
+        self.h = h
+        self.grad = torch.zeros(MLP_NPARAMS, dtype=torch.float32, device=self.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        self.ws = Workspace(self.device)
+
+    def set_params(self, p):
+        import numpy as np
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        _check(_lib.lms_mlp_set_params(self.h, a.ctypes.data))
+
+    def get_params(self):
+        import numpy as np
+        a = np.zeros(MLP_NPARAMS, np.float32)
+        _check(_lib.lms_mlp_get_params(self.h, a.ctypes.data))
+        return a
+
+    def loss_grad_async(self, X, T, M, stream=None):
+        n = int(X.shape[0])
+        ws = self.ws.get(_lib.lms_mlp_workspace(n))
+        _check(_lib.lms_mlp_loss_grad(self.h, X.data_ptr(), T.data_ptr(), M.data_ptr(), n, self.grad.data_ptr(),
+                                      self.loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream)))
+
+    def loss_grad(self, X, T, M, stream=None):
+        """Loss (float) and gradient (numpy) of the masked squared error (synchronises)."""
+        self.loss_grad_async(X, T, M, stream)
+        torch.cuda.synchronize()
+        return float(self.loss.item()), self.grad.cpu().numpy()
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_lib.lms_mlp_adam_step(self.h, self.grad.data_ptr(), lr, beta1, beta2, eps, _stream_handle(stream)))
+
+    def forward(self, X, bf16=False, stream=None):
+        n = int(X.shape[0])
+        y = torch.empty(max(n, 1), 2, dtype=torch.float32, device=self.device)
+        _check(_lib.lms_mlp_forward(self.h, X.data_ptr(), n, y.data_ptr(), 1 if bf16 else 0, _stream_handle(stream)))
+        return y[:n]
+
+    def free(self):
+        if self.h:
+            _lib.lms_mlp_free(self.h)
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

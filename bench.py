@@ -43,7 +43,94 @@ def parse():
     ap.add_argument("--no-trace", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--calib", action="store_true",
                     help="also run a 256 MiB device-to-device copy (scale reference for HBM byte counters)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-stream comparison")
+    ap.add_argument("--batches", type=int, default=256)
+    ap.add_argument("--tuning", default=None, help="tuning JSON written by the autotuner (default: the packaged one)")
     return ap.parse_args()
+
+
+def run_batched(args, torch, lms, datagen, cols, dev):
+    """256 micro-batches with log-uniform row counts in [1K, 8M], sliced from the
+    resident 16M-row pool, through the tumbling-window query (val < 500,
+    v2 = val * 2, key x 1 s, COUNT and SUM(v2)): one launch sequence per batch
+    against one persistent launch per stage over all batches, eager and replayed
+    from a captured graph.  Results are compared per batch (bit-exact)."""
+    from paper_2111_04289_amd import autotune
+    tuned = autotune.apply("batched", args.tuning)
+    rng = np.random.default_rng(11)
+    pool_n = int(cols[0].shape[0])
+    hi = min(8 << 20, pool_n)
+    sizes = np.exp(rng.uniform(np.log(1024), np.log(hi), args.batches)).astype(np.int64)
+    offs = [int(rng.integers(0, pool_n - s + 1)) for s in sizes]
+    batches = [[c[o:o + int(s)] for c in cols] for o, s in zip(offs, sizes)]
+    total = int(sizes.sum())
+    preds, projs = [(2, lms.LT, 500)], [(2, 2, 0)]
+    aggs = [(lms.COUNT, 0), (lms.SUM, 4)]
+    w = lms.Window(0, 1000, 0, 0)
+    log(f"batched: {args.batches} batches, {total} rows, tuning {tuned}")
+
+    single_groups = [lms.Groups(int(s), aggs, dev) for s in sizes]
+    single_cnt = torch.zeros((args.batches, 2), dtype=torch.int64, device=dev)
+    ws = lms.Workspace(dev)
+    ws.get(max(lms.lms_window_agg_workspace(b, 1, w, aggs) for b in batches))
+
+    def per_batch():
+        for b in range(args.batches):
+            lms.lms_window_agg(batches[b], 1, w, aggs, preds, projs, groups=single_groups[b],
+                               d_count=single_cnt[b], workspace=ws)
+
+    job = lms.MultiJob(1, w, aggs, preds, projs, device=dev)
+    mgroups, mcnt = job.prepare(batches)
+    job.freeze()
+    job.launch()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        job.launch()
+
+    def timed(fn, reps):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    reps = max(3, min(args.steps, 10))
+    ms_single = timed(per_batch, reps)
+    ms_multi = timed(job.launch, reps)
+    ms_graph = timed(graph.replay, reps)
+
+    # per-batch bit-exact comparison (multi graph result vs one launch sequence per batch)
+    torch.cuda.synchronize()
+    sc, mc = single_cnt.cpu().numpy(), mcnt.cpu().numpy()
+    exact = bool((sc == mc).all()) and not sc[:, 1].any()
+    if exact:
+        for b in range(args.batches):
+            m = int(sc[b, 0])
+            rows = []
+            for g in (single_groups[b], mgroups[b]):
+                t = torch.stack([g.key[:m], g.wstart[:m]] + [a[:m] for a in g.aggs]).cpu().numpy()
+                rows.append(t[:, np.lexsort(t[::-1])])
+            if not np.array_equal(rows[0], rows[1]):
+                exact = False
+                break
+    res = {"batches": args.batches, "rows": total, "min_rows": int(sizes.min()), "max_rows": int(sizes.max()),
+           "groups": int(sc[:, 0].sum()), "per_batch_ms": round(ms_single, 3), "persistent_ms": round(ms_multi, 3),
+           "persistent_graph_ms": round(ms_graph, 3),
+           "per_batch_Mrows_s": round(total / ms_single / 1e3, 1),
+           "persistent_graph_Mrows_s": round(total / ms_graph / 1e3, 1),
+           "speedup": round(ms_single / ms_graph, 3), "bit_exact_per_batch": exact, "tuning": tuned}
+    log(f"batched {res}")
+    del graph, job, mgroups, single_groups
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    lms.set_tuning()
+    return res
 
 
 def main():
@@ -65,6 +152,12 @@ def main():
     cols = [torch.from_numpy(c).to(dev) for c in cols_np]
     bk, bp = torch.from_numpy(bk_np).to(dev), torch.from_numpy(bp_np).to(dev)
 
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(args, torch, lms, datagen, cols, dev)
+
+    from paper_2111_04289_amd import autotune
+    tuned = autotune.apply("sliding", args.tuning)
     preds = [(2, lms.LT, cut)]
     aggs = [(lms.COUNT, 0), (lms.SUM, 2), (lms.MIN, 2), (lms.MAX, 2), (lms.AVG, 3)]
     window = lms.Window(0, 10000, 1000, 0)
@@ -191,6 +284,8 @@ def main():
         "ops": ops,
         "join_build_ms": round(build_ms, 3),
         "window_status": status,
+        "tuning": tuned,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

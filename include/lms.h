@@ -176,6 +176,54 @@ int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, co
                    int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg, const lms_groups* out,
                    int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream);
 
+/* ---- Many micro-batches per launch -------------------------------------------
+ * The same windowed group-by over nbatch micro-batches of one schema, with
+ * every stage run as one persistent launch over all batches (a fixed grid
+ * whose workgroups loop over (batch, chunk), (batch, partition) and
+ * (batch, item) work).  lms_window_agg_multi_prepare validates the batches and
+ * writes per-batch descriptors into the workspace (an upload ordered on
+ * `stream` from the library's pinned staging; the caller's host arrays may be
+ * reused as soon as it returns; not capturable) and fills *cfg;
+ * lms_window_agg_multi_launch enqueues the seven launches, which read
+ * everything from the workspace, so a graph captured around it can be
+ * replayed after another prepare into the same workspace (new batches, sizes
+ * or outputs).  The kernels compare the prepared job with the limits the
+ * launch was configured for (LDS of cfg->max_nparts partitions and
+ * cfg->agg_lds bytes, cfg->ma aggregates); a job beyond them does nothing but
+ * set status LMS_EINVAL in every d_counts pair.  outs[b] and
+ * d_counts[2b..2b+1] receive batch b's result exactly as lms_window_agg would
+ * (same groups and values; the order of rows may differ).  The workspace
+ * must stay untouched until the launch completes. */
+typedef struct {
+  int32_t nbatch;
+  int32_t ma;         /* aggregate unroll bound of the kernels (2, 4, 6 or 8) */
+  int32_t max_nparts; /* largest partition count of a batch */
+  int32_t grid_scan;  /* persistent workgroups of the scan stages */
+  int32_t grid_agg;   /* persistent workgroups of the aggregation stages */
+  int32_t reserved;
+  uint64_t agg_lds; /* dynamic LDS bytes of an aggregation workgroup */
+} lms_multi_config;
+size_t lms_window_agg_multi_workspace(const lms_batch* batches, int32_t nbatch, int32_t key_col, const lms_window* w,
+                                      const lms_agg* aggs, int32_t nagg);
+int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nbatch, const lms_pred* preds, int32_t npred,
+                                 const lms_proj* projs, int32_t nproj, int32_t key_col, const lms_window* w,
+                                 const lms_agg* aggs, int32_t nagg, const lms_groups* outs, int64_t* d_counts,
+                                 void* workspace, size_t ws_bytes, lms_multi_config* cfg, lms_stream stream);
+int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lms_stream stream);
+
+/* Tile and schedule parameters of the windowed group-by (process-wide; NULL
+ * or 0 fields select the defaults): rows per scan chunk, target rows per
+ * partition, rows per aggregation piece (>= 1024), persistent scan workgroups
+ * per CU.  Chosen by the project's autotuner. */
+typedef struct {
+  int32_t chunk_rows;
+  int32_t part_rows;
+  int32_t piece_rows;
+  int32_t grid_per_cu;
+} lms_tuning;
+int lms_set_tuning(const lms_tuning* t);
+int lms_get_tuning(lms_tuning* t);
+
 /* ---- Stream-static hash join (Table II "Join (Hash)"; the join of LR1 in
  * Table III) ---------------------------------------------------------------
  * lms_join_build hashes the static table `tbl` on integer column key_col and

@@ -25,6 +25,7 @@
 //    sub-ranges of a second key hash (halving until it fits).
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "lms_internal.h"
 
@@ -113,8 +114,8 @@ __device__ __forceinline__ uint64_t div_pane(uint64_t rel, int64_t pane, double 
 
 // ---- kernels 1-4: partition rows by key hash --------------------------------
 
-__global__ void k_wa_init(WinArgs a) {
-  if (threadIdx.x == 0) {
+__device__ __forceinline__ void init_batch(const WinArgs& a) {
+  {
     a.d_count[0] = 0;
     a.d_count[1] = 0;
     a.hdr[1] = 0;
@@ -128,11 +129,15 @@ __global__ void k_wa_init(WinArgs a) {
   }
 }
 
-__global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
-  extern __shared__ uint32_t hist[];
+__global__ void k_wa_init(WinArgs a) {
+  if (threadIdx.x == 0) init_batch(a);
+}
+
+// LDS histogram of the passing rows of chunk w over the partitions.
+__device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) hist[p] = 0;
   __syncthreads();
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t lo = (int64_t)w * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   const void* kc = a.q.col[a.key_col];
   const int kdt = a.q.dt[a.key_col];
@@ -153,24 +158,31 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
       if (ok[u]) atomicAdd(&hist[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) a.H[(size_t)p * a.g1 + blockIdx.x] = hist[p];
+  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) a.H[(size_t)p * a.g1 + w] = hist[p];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
+  extern __shared__ uint32_t hist[];
+  hist_chunk(a, blockIdx.x, hist);
 }
 
 // Rows per partition.
-__global__ __launch_bounds__(kScanTPB) void k_wa_scan1(WinArgs a) {
-  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
-  const int p = blockIdx.x;
+__device__ void scan1_part(const WinArgs& a, int p, uint32_t* scratch) {
   uint32_t s = 0;
   for (int w = threadIdx.x; w < a.g1; w += kScanTPB) s += a.H[(size_t)p * a.g1 + w];
   s = block_sum<kScanTPB>(s, scratch);
   if (threadIdx.x == 0) a.Rp[p] = s;
 }
 
+__global__ __launch_bounds__(kScanTPB) void k_wa_scan1(WinArgs a) {
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  scan1_part(a, blockIdx.x, scratch);
+}
+
 // Partition starts, per-(partition, chunk) write offsets and the work items of
 // the aggregation (a partition of R rows gives ceil(R / rs) items).
-__global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
-  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
-  const int p = blockIdx.x;
+__device__ void scan2_part(const WinArgs& a, int p, uint32_t* scratch) {
   uint32_t s_rows = 0, s_items = 0;
   for (int q = threadIdx.x; q < p; q += kScanTPB) {
     const uint32_t r = a.Rp[q];
@@ -223,6 +235,12 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
     a.pfill[p] = 0;
     if (p == a.nparts - 1) a.hdr[1] = ibase + kp;
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  scan2_part(a, blockIdx.x, scratch);
 }
 
 // Raw bits of staged value column v at row i (int64, or the float's own bits).
@@ -240,12 +258,11 @@ __device__ __forceinline__ uint64_t staged_bits(const WinArgs& a, int v, int64_t
 // Every column a row needs is loaded for all kUnroll rows of a thread before
 // the first LDS cursor atomic, so the loads overlap.
 template <int MA>
-__global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
-  extern __shared__ uint32_t cursor[];
-  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) cursor[p] = a.Off[(size_t)p * a.g1 + blockIdx.x];
+__device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
+  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
   __syncthreads();
   const int64_t b0 = a.hdr[0];
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t lo = (int64_t)w * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   const void* kc = a.q.col[a.key_col];
   const int kdt = a.q.dt[a.key_col];
@@ -290,6 +307,13 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
     }
   }
   if (range_err) set_device_status(a.d_count, LMS_ERANGE);
+  __syncthreads();
+}
+
+template <int MA>
+__global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
+  extern __shared__ uint32_t cursor[];
+  scatter_chunk<MA>(a, blockIdx.x, cursor);
 }
 
 // LDS layout of one aggregation workgroup.
@@ -859,10 +883,8 @@ __device__ void aggregate_piece(const WinArgs& a, Lds& s, const Item& it) {
 }
 
 template <int MA>
-__global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
-  const uint32_t item = blockIdx.x;
+__device__ void agg_item(const WinArgs& a, uint32_t item, char* lds_raw) {
   if ((int64_t)item >= a.hdr[1]) return;
-  extern __shared__ __align__(16) char lds_raw[];
   Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
   const Item it = a.items[item];
   if (it.kp > 1) {
@@ -871,16 +893,201 @@ __global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
     Segments sg{false, it.lo, it.hi};
     aggregate_and_emit<MA>(a, s, sg);
   }
+  __syncthreads();
+}
+
+template <int MA>
+__device__ void merge_part(const WinArgs& a, uint32_t p, char* lds_raw) {
+  const PartInfo pi = a.pinfo[p];
+  if (pi.kp <= 1) return;
+  Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
+  Segments sg{true, pi.start, pi.start + a.pfill[p]};
+  aggregate_and_emit<MA>(a, s, sg);
+  __syncthreads();
+}
+
+template <int MA>
+__global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
+  extern __shared__ __align__(16) char lds_raw[];
+  agg_item<MA>(a, blockIdx.x, lds_raw);
 }
 
 template <int MA>
 __global__ __launch_bounds__(kAggTPB) void k_wa_merge(WinArgs a) {
-  const PartInfo pi = a.pinfo[blockIdx.x];
-  if (pi.kp <= 1) return;
   extern __shared__ __align__(16) char lds_raw[];
-  Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
-  Segments sg{true, pi.start, pi.start + a.pfill[blockIdx.x]};
-  aggregate_and_emit<MA>(a, s, sg);
+  merge_part<MA>(a, blockIdx.x, lds_raw);
+}
+
+
+// ---- many micro-batches in one persistent launch per stage ---------------------
+//
+// The per-batch arguments (one WinArgs per batch, each with its own workspace
+// slice and outputs) live in device memory with prefix tables that map a
+// global chunk / partition / item index to its batch.  Every stage is one
+// launch of a fixed grid whose workgroups loop over the global indices, so the
+// launch sequence depends only on that grid and can be captured once in a
+// graph and replayed after the descriptors are rewritten for the next job.
+
+struct MultiHdr {
+  uint32_t nb;
+  uint32_t nchunks;     // total scan chunks
+  uint32_t nparts;      // total partitions
+  uint32_t nitems;      // total aggregation item slots (per batch: its bound)
+  uint32_t max_nparts;  // largest partition count of a batch
+  uint32_t agg_lds;     // largest aggregation LDS plan of a batch
+  uint32_t max_nagg;    // largest aggregate count of a batch
+  uint32_t reserved[9];
+};
+
+// Limits a launch was configured for (LDS it was given, unroll bound).
+struct MultiLim {
+  uint32_t parts, agg_lds, ma, pad;
+};
+
+// A job whose descriptors exceed what the launch was configured for (a graph
+// replayed after a larger job was prepared) is rejected as a whole.
+__device__ __forceinline__ bool multi_fits(const MultiHdr* h, MultiLim l) {
+  return h->max_nparts <= l.parts && h->agg_lds <= l.agg_lds && h->max_nagg <= l.ma;
+}
+
+struct MultiView {
+  const MultiHdr* hdr;
+  const uint32_t* cpre;  // nb + 1 chunk prefix
+  const uint32_t* ppre;  // nb + 1 partition prefix
+  const uint32_t* ipre;  // nb + 1 item-slot prefix
+  const WinArgs* args;   // nb
+};
+
+__device__ __forceinline__ MultiView multi_view(const char* desc) {
+  MultiView v;
+  v.hdr = (const MultiHdr*)desc;
+  const uint32_t nb = v.hdr->nb;
+  size_t o = sizeof(MultiHdr);
+  v.cpre = (const uint32_t*)(desc + o);
+  o += align_up((size_t)(nb + 1) * 4, 16);
+  v.ppre = (const uint32_t*)(desc + o);
+  o += align_up((size_t)(nb + 1) * 4, 16);
+  v.ipre = (const uint32_t*)(desc + o);
+  o += align_up((size_t)(nb + 1) * 4, 16);
+  v.args = (const WinArgs*)(desc + align_up(o, 16));
+  return v;
+}
+
+// Batch owning global index g: the last b with pre[b] <= g.
+__device__ __forceinline__ uint32_t batch_of(const uint32_t* pre, uint32_t nb, uint32_t g) {
+  uint32_t lo = 0, hi = nb - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Copies batch b's arguments into the workgroup's LDS copy when it changes.
+__device__ __forceinline__ void load_args(const MultiView& v, uint32_t b, WinArgs* sa, uint32_t* cur) {
+  if (*cur == b) return;
+  __syncthreads();
+  const uint32_t* src = (const uint32_t*)&v.args[b];
+  uint32_t* dst = (uint32_t*)sa;
+  for (uint32_t i = threadIdx.x; i < sizeof(WinArgs) / 4; i += blockDim.x) dst[i] = src[i];
+  *cur = b;
+  __syncthreads();
+}
+
+__global__ void k_wam_init(const char* desc, MultiLim lim) {
+  const MultiView v = multi_view(desc);
+  const bool fits = multi_fits(v.hdr, lim);
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < v.hdr->nb; b += gridDim.x * blockDim.x) {
+    init_batch(v.args[b]);
+    if (!fits) v.args[b].d_count[1] = LMS_EINVAL;
+  }
+}
+
+__global__ __launch_bounds__(kScanTPB) void k_wam_hist(const char* desc, MultiLim lim) {
+  extern __shared__ uint32_t hist[];
+  __shared__ WinArgs sa;
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  uint32_t cur = ~0u;
+  for (uint32_t g = blockIdx.x; g < v.hdr->nchunks; g += gridDim.x) {
+    const uint32_t b = batch_of(v.cpre, v.hdr->nb, g);
+    load_args(v, b, &sa, &cur);
+    hist_chunk(sa, g - v.cpre[b], hist);
+  }
+}
+
+__global__ __launch_bounds__(kScanTPB) void k_wam_scan1(const char* desc, MultiLim lim) {
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  __shared__ WinArgs sa;
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  uint32_t cur = ~0u;
+  for (uint32_t g = blockIdx.x; g < v.hdr->nparts; g += gridDim.x) {
+    const uint32_t b = batch_of(v.ppre, v.hdr->nb, g);
+    load_args(v, b, &sa, &cur);
+    scan1_part(sa, (int)(g - v.ppre[b]), scratch);
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kScanTPB) void k_wam_scan2(const char* desc, MultiLim lim) {
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  __shared__ WinArgs sa;
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  uint32_t cur = ~0u;
+  for (uint32_t g = blockIdx.x; g < v.hdr->nparts; g += gridDim.x) {
+    const uint32_t b = batch_of(v.ppre, v.hdr->nb, g);
+    load_args(v, b, &sa, &cur);
+    scan2_part(sa, (int)(g - v.ppre[b]), scratch);
+  }
+}
+
+template <int MA>
+__global__ __launch_bounds__(kScanTPB) void k_wam_scatter(const char* desc, MultiLim lim) {
+  extern __shared__ uint32_t cursor[];
+  __shared__ WinArgs sa;
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  uint32_t cur = ~0u;
+  for (uint32_t g = blockIdx.x; g < v.hdr->nchunks; g += gridDim.x) {
+    const uint32_t b = batch_of(v.cpre, v.hdr->nb, g);
+    load_args(v, b, &sa, &cur);
+    scatter_chunk<MA>(sa, g - v.cpre[b], cursor);
+  }
+}
+
+template <int MA>
+__global__ __launch_bounds__(kAggTPB) void k_wam_agg(const char* desc, MultiLim lim) {
+  extern __shared__ __align__(16) char lds_raw[];
+  __shared__ WinArgs sa;
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  uint32_t cur = ~0u;
+  for (uint32_t g = blockIdx.x; g < v.hdr->nitems; g += gridDim.x) {
+    const uint32_t b = batch_of(v.ipre, v.hdr->nb, g);
+    const uint32_t item = g - v.ipre[b];
+    if ((int64_t)item >= v.args[b].hdr[1]) continue;  // slot beyond this batch's items
+    load_args(v, b, &sa, &cur);
+    agg_item<MA>(sa, item, lds_raw);
+  }
+}
+
+template <int MA>
+__global__ __launch_bounds__(kAggTPB) void k_wam_merge(const char* desc, MultiLim lim) {
+  extern __shared__ __align__(16) char lds_raw[];
+  __shared__ WinArgs sa;
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  uint32_t cur = ~0u;
+  for (uint32_t g = blockIdx.x; g < v.hdr->nparts; g += gridDim.x) {
+    const uint32_t b = batch_of(v.ppre, v.hdr->nb, g);
+    const uint32_t p = g - v.ppre[b];
+    if (v.args[b].pinfo[p].kp <= 1) continue;
+    load_args(v, b, &sa, &cur);
+    merge_part<MA>(sa, p, lds_raw);
+  }
 }
 
 // ---- host planning -------------------------------------------------------------
@@ -918,18 +1125,22 @@ int64_t gcd64(int64_t x, int64_t y) {
   return x;
 }
 
+lms_tuning g_tuning{0, 0, 0, 0};
+
 Plan make_plan(int64_t n, int nval, int nacc) {
   Plan p{};
   p.n = n;
-  p.chunk = std::min<int64_t>(65536, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
+  if (g_tuning.chunk_rows > 0) p.chunk = next_pow2(g_tuning.chunk_rows);
+  else p.chunk = std::min<int64_t>(65536, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
   p.g1 = (int)((n + p.chunk - 1) / p.chunk);
-  p.nparts = (int)std::min<int64_t>(4096, std::max<int64_t>(8, next_pow2((n + 16383) / 16384)));
+  const int64_t part_rows = g_tuning.part_rows > 0 ? g_tuning.part_rows : 16384;
+  p.nparts = (int)std::min<int64_t>(4096, std::max<int64_t>(8, next_pow2((n + part_rows - 1) / part_rows)));
   p.pbits = ilog2(p.nparts);
-  p.rs = 8192;
+  p.rs = g_tuning.piece_rows > 0 ? g_tuning.piece_rows : 8192;
   p.max_items = p.nparts + (int)((n + p.rs - 1) / p.rs);
   p.eg = 2048;
   p.ek = 1024;
-  while (lds_bytes(p.ek, p.eg, nacc) > (size_t)kLdsLimit && p.eg > 1024) {
+  while (lds_bytes(p.ek, p.eg, nacc) + sizeof(WinArgs) > (size_t)kLdsLimit && p.eg > 1024) {
     p.eg /= 2;
     p.ek /= 2;
   }
@@ -1072,13 +1283,17 @@ extern "C" size_t lms_window_agg_workspace(const lms_batch* in, int32_t key_col,
   return carve_workspace(make_plan(in->nrows, nval, nacc), nullptr, nullptr);
 }
 
-extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs,
-                              int32_t nproj, int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg,
-                              const lms_groups* out, int64_t* d_count, void* workspace, size_t ws_bytes,
-                              lms_stream stream) {
+namespace lms {
+namespace {
+
+// Validates one batch's call and fills its kernel arguments, carving `workspace`.
+int setup_args(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs, int32_t nproj,
+               int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg, const lms_groups* out,
+               int64_t* d_count, void* workspace, size_t ws_bytes, WinArgs* pa, Plan* pplan) {
   int rc = validate_window(in, key_col, w);
   if (rc) return rc;
-  WinArgs a{};
+  WinArgs& a = *pa;
+  a = WinArgs{};
   rc = build_query(in, preds, npred, projs, nproj, &a.q);
   if (rc) return rc;
   rc = resolve_aggs(in, projs, nproj, aggs, nagg, &a);
@@ -1090,13 +1305,11 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
   for (int k = 0; k < nagg; ++k)
     if (out->cap > 0 && !out->aggs[k]) return set_error(LMS_EINVAL, "output aggregate %d is NULL", k);
   if (!d_count) return set_error(LMS_EINVAL, "d_count is NULL");
-
   const Plan p = make_plan(in->nrows, a.nval, a.nacc);
   const size_t need = carve_workspace(p, nullptr, nullptr);
   if (!workspace || ws_bytes < need)
     return set_error(LMS_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, need);
   carve_workspace(p, workspace, &a);
-
   a.key_col = key_col;
   a.ts_col = w->ts_col;
   a.len = w->len;
@@ -1120,7 +1333,70 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
   for (int k = 0; k < nagg; ++k) a.oagg[k] = out->aggs[k];
   a.cap = out->cap;
   a.d_count = d_count;
+  *pplan = p;
+  return LMS_OK;
+}
 
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+
+// Pinned staging of the multi-batch descriptors: the upload is asynchronous,
+// so the next prepare waits for the previous upload before reusing the buffer.
+struct DescStage {
+  std::mutex mu;
+  char* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+DescStage g_stage;
+
+size_t multi_desc_bytes(int nb) {
+  size_t o = sizeof(MultiHdr) + 3 * align_up((size_t)(nb + 1) * 4, 16);
+  return align_up(align_up(o, 16) + (size_t)nb * sizeof(WinArgs), 256);
+}
+
+template <int MA>
+void launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
+  static bool attr_done = false;
+  if (!attr_done) {
+    (void)hipFuncSetAttribute((const void*)k_wam_agg<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsLimit - (int)sizeof(WinArgs));
+    (void)hipFuncSetAttribute((const void*)k_wam_merge<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kLdsLimit - (int)sizeof(WinArgs));
+    attr_done = true;
+  }
+  const size_t plds = (size_t)c.max_nparts * 4;
+  const MultiLim lim{(uint32_t)c.max_nparts, (uint32_t)c.agg_lds, (uint32_t)MA, 0};
+  LMS_LAUNCH("k_wam_init", k_wam_init, dim3(4), dim3(256), 0, st, desc, lim);
+  LMS_LAUNCH("k_wam_hist", k_wam_hist, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
+  LMS_LAUNCH("k_wam_scan1", k_wam_scan1, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
+  LMS_LAUNCH("k_wam_scan2", k_wam_scan2, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
+  LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
+  LMS_LAUNCH("k_wam_agg", k_wam_agg<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
+  LMS_LAUNCH("k_wam_merge", k_wam_merge<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
+}
+
+}  // namespace
+}  // namespace lms
+
+extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs,
+                              int32_t nproj, int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg,
+                              const lms_groups* out, int64_t* d_count, void* workspace, size_t ws_bytes,
+                              lms_stream stream) {
+  WinArgs a;
+  Plan p;
+  int rc = setup_args(in, preds, npred, projs, nproj, key_col, w, aggs, nagg, out, d_count, workspace, ws_bytes, &a, &p);
+  if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
   LMS_LAUNCH("k_wa_init", k_wa_init, dim3(1), dim3(64), 0, st, a);
   if (in->nrows > 0) {
@@ -1135,4 +1411,137 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
     else launch_tail<8>(p, a, plds, st);
   }
   return check_hip(hipGetLastError(), "window_agg launch");
+}
+
+extern "C" int lms_set_tuning(const lms_tuning* t) {
+  if (!t) {
+    g_tuning = lms_tuning{0, 0, 0, 0};
+    return LMS_OK;
+  }
+  if (t->chunk_rows < 0 || t->part_rows < 0 || t->piece_rows < 0 || t->grid_per_cu < 0)
+    return set_error(LMS_EINVAL, "tuning values must be >= 0");
+  if (t->piece_rows > 0 && t->piece_rows < 1024) return set_error(LMS_EINVAL, "piece_rows must be >= 1024");
+  g_tuning = *t;
+  return LMS_OK;
+}
+
+extern "C" int lms_get_tuning(lms_tuning* t) {
+  if (!t) return set_error(LMS_EINVAL, "NULL");
+  *t = g_tuning;
+  return LMS_OK;
+}
+
+extern "C" size_t lms_window_agg_multi_workspace(const lms_batch* batches, int32_t nbatch, int32_t key_col,
+                                                 const lms_window* w, const lms_agg* aggs, int32_t nagg) {
+  if (!batches || nbatch <= 0) return 0;
+  size_t total = multi_desc_bytes(nbatch);
+  for (int b = 0; b < nbatch; ++b) {
+    const size_t one = lms_window_agg_workspace(&batches[b], key_col, w, aggs, nagg);
+    if (one == 0) return 0;
+    total += align_up(one, 256);
+  }
+  return total;
+}
+
+extern "C" int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nbatch, const lms_pred* preds,
+                                            int32_t npred, const lms_proj* projs, int32_t nproj, int32_t key_col,
+                                            const lms_window* w, const lms_agg* aggs, int32_t nagg,
+                                            const lms_groups* outs, int64_t* d_counts, void* workspace,
+                                            size_t ws_bytes, lms_multi_config* cfg, lms_stream stream) {
+  if (!batches || nbatch <= 0 || !outs || !d_counts || !cfg || !workspace)
+    return set_error(LMS_EINVAL, "bad multi-batch arguments");
+  const size_t dbytes = multi_desc_bytes(nbatch);
+  if (ws_bytes < dbytes) return set_error(LMS_ENOMEM, "workspace too small");
+  std::lock_guard<std::mutex> lk(g_stage.mu);
+  if (g_stage.pending) {
+    int rc = check_hip(hipEventSynchronize(g_stage.done), "descriptor staging wait");
+    if (rc) return rc;
+    g_stage.pending = false;
+  }
+  if (!g_stage.done) {
+    int rc = check_hip(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming), "event create");
+    if (rc) return rc;
+  }
+  if (g_stage.cap < dbytes) {
+    if (g_stage.host) (void)hipHostFree(g_stage.host);
+    g_stage.host = nullptr;
+    g_stage.cap = 0;
+    int rc = check_hip(hipHostMalloc((void**)&g_stage.host, dbytes, hipHostMallocDefault), "pinned staging");
+    if (rc) return rc;
+    g_stage.cap = dbytes;
+  }
+  std::memset(g_stage.host, 0, dbytes);
+  char* const hbuf = g_stage.host;
+  MultiHdr* hdr = (MultiHdr*)hbuf;
+  hdr->nb = (uint32_t)nbatch;
+  size_t o = sizeof(MultiHdr);
+  uint32_t* cpre = (uint32_t*)(hbuf + o);
+  o += align_up((size_t)(nbatch + 1) * 4, 16);
+  uint32_t* ppre = (uint32_t*)(hbuf + o);
+  o += align_up((size_t)(nbatch + 1) * 4, 16);
+  uint32_t* ipre = (uint32_t*)(hbuf + o);
+  o += align_up((size_t)(nbatch + 1) * 4, 16);
+  WinArgs* args = (WinArgs*)(hbuf + align_up(o, 16));
+  size_t off = dbytes;
+  int max_nparts = 1;
+  uint64_t c = 0, pp = 0, it = 0;
+  size_t agg_lds = 0;
+  for (int b = 0; b < nbatch; ++b) {
+    Plan p;
+    const size_t remain = ws_bytes > off ? ws_bytes - off : 0;
+    int rc = setup_args(&batches[b], preds, npred, projs, nproj, key_col, w, aggs, nagg, &outs[b], d_counts + 2 * b,
+                        (char*)workspace + off, remain, &args[b], &p);
+    if (rc) return rc;
+    off += align_up(carve_workspace(p, nullptr, nullptr), 256);
+    cpre[b] = (uint32_t)c;
+    ppre[b] = (uint32_t)pp;
+    ipre[b] = (uint32_t)it;
+    c += (uint64_t)p.g1;
+    pp += (uint64_t)p.nparts;
+    it += (uint64_t)p.max_items;
+    max_nparts = std::max(max_nparts, p.nparts);
+    agg_lds = std::max(agg_lds, p.lds);
+  }
+  if (c >= (1ull << 32) || pp >= (1ull << 32) || it >= (1ull << 32)) return set_error(LMS_EINVAL, "job too large");
+  cpre[nbatch] = (uint32_t)c;
+  ppre[nbatch] = (uint32_t)pp;
+  ipre[nbatch] = (uint32_t)it;
+  hdr->nchunks = (uint32_t)c;
+  hdr->nparts = (uint32_t)pp;
+  hdr->nitems = (uint32_t)it;
+  hdr->max_nparts = (uint32_t)max_nparts;
+  hdr->agg_lds = (uint32_t)agg_lds;
+  hdr->max_nagg = (uint32_t)std::max(nagg, 0);
+  cfg->nbatch = nbatch;
+  cfg->ma = nagg <= 2 ? 2 : nagg <= 4 ? 4 : nagg <= 6 ? 6 : 8;
+  cfg->max_nparts = max_nparts;
+  const int per_cu = g_tuning.grid_per_cu > 0 ? g_tuning.grid_per_cu : 4;
+  cfg->grid_scan = num_cus() * per_cu;
+  cfg->grid_agg = num_cus();
+  cfg->reserved = 0;
+  cfg->agg_lds = agg_lds;
+  int rc = check_hip(hipMemcpyAsync(workspace, hbuf, dbytes, hipMemcpyHostToDevice, (hipStream_t)stream),
+                     "descriptor upload");
+  if (rc) return rc;
+  rc = check_hip(hipEventRecord(g_stage.done, (hipStream_t)stream), "descriptor upload event");
+  if (rc) return rc;
+  g_stage.pending = true;
+  return LMS_OK;
+}
+
+extern "C" int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lms_stream stream) {
+  if (!cfg || !workspace || cfg->nbatch <= 0) return set_error(LMS_EINVAL, "bad multi-batch launch arguments");
+  if (cfg->grid_scan <= 0 || cfg->grid_agg <= 0 || cfg->max_nparts <= 0 || cfg->max_nparts > 4096 ||
+      cfg->agg_lds > (uint64_t)(kLdsLimit - (int)sizeof(WinArgs)) ||
+      !(cfg->ma == 2 || cfg->ma == 4 || cfg->ma == 6 || cfg->ma == 8))
+    return set_error(LMS_EINVAL, "bad multi-batch configuration");
+  hipStream_t st = (hipStream_t)stream;
+  const char* desc = (const char*)workspace;
+  switch (cfg->ma) {
+    case 2: launch_multi<2>(*cfg, desc, st); break;
+    case 4: launch_multi<4>(*cfg, desc, st); break;
+    case 6: launch_multi<6>(*cfg, desc, st); break;
+    case 8: launch_multi<8>(*cfg, desc, st); break;
+  }
+  return check_hip(hipGetLastError(), "multi-batch launch");
 }

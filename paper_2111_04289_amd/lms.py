@@ -100,6 +100,17 @@ class lms_trace_stat(ctypes.Structure):
                 ("min_ms", ctypes.c_double), ("max_ms", ctypes.c_double)]
 
 
+class lms_multi_config(ctypes.Structure):
+    _fields_ = [("nbatch", ctypes.c_int32), ("ma", ctypes.c_int32), ("max_nparts", ctypes.c_int32),
+                ("grid_scan", ctypes.c_int32), ("grid_agg", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("agg_lds", ctypes.c_uint64)]
+
+
+class lms_tuning(ctypes.Structure):
+    _fields_ = [("chunk_rows", ctypes.c_int32), ("part_rows", ctypes.c_int32), ("piece_rows", ctypes.c_int32),
+                ("grid_per_cu", ctypes.c_int32)]
+
+
 _P = ctypes.POINTER
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 _SIGS = {
@@ -112,6 +123,13 @@ _SIGS = {
     "lms_window_agg_pane_limit": (_i64, [_i32]),
     "lms_window_agg": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _i32, _P(lms_window),
                                       _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz, _vp]),
+    "lms_window_agg_multi_workspace": (_sz, [_P(lms_batch), _i32, _i32, _P(lms_window), _P(lms_agg), _i32]),
+    "lms_window_agg_multi_prepare": (ctypes.c_int, [_P(lms_batch), _i32, _P(lms_pred), _i32, _P(lms_proj), _i32, _i32,
+                                                    _P(lms_window), _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz,
+                                                    _P(lms_multi_config), _vp]),
+    "lms_window_agg_multi_launch": (ctypes.c_int, [_P(lms_multi_config), _vp, _vp]),
+    "lms_set_tuning": (ctypes.c_int, [_P(lms_tuning)]),
+    "lms_get_tuning": (ctypes.c_int, [_P(lms_tuning)]),
     "lms_join_build": (ctypes.c_int, [_P(lms_batch), _i32, _i32, _P(_vp), _vp]),
     "lms_join_max_mult": (_i64, [_vp]),
     "lms_join_build_rows": (_i64, [_vp]),
@@ -315,6 +333,105 @@ def lms_window_agg(cols, key_col, window: Window, aggs, preds=(), projs=(), grou
                              _stream_handle(stream))
     _check(rc)
     return groups, d_count
+
+
+class MultiJob:
+    """The windowed group-by of many micro-batches, one persistent launch per stage.
+
+    ``prepare`` writes the batches' descriptors into the job's workspace (and
+    may be called again with other batches of the same schema); ``launch``
+    enqueues the kernels, which read only the workspace, so it can be captured
+    in a graph once and replayed after each ``prepare``.  Batch b's result is in
+    ``groups[b]`` and ``d_counts[b]`` ([count, status]).
+    """
+
+    def __init__(self, key_col, window: Window, aggs, preds=(), projs=(), device=None):
+        self.key_col, self.window, self.aggs = key_col, window, list(aggs)
+        self.preds, self.projs = list(preds), list(projs)
+        self.device = device or torch.device("cuda")
+        self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+        self.cfg = lms_multi_config()
+        self.launch_cfg = None  # the limits launches are configured for
+        self._keep = None
+
+    def _arrays(self, batches):
+        bs = [_Batch(c) for c in batches]
+        arr = (lms_batch * len(bs))(*[b.batch for b in bs])
+        aa = (lms_agg * max(1, len(self.aggs)))(*[lms_agg(f, c) for f, c in self.aggs])
+        return bs, arr, aa
+
+    def workspace_bytes(self, batches) -> int:
+        bs, arr, aa = self._arrays(batches)
+        w = self.window.c()
+        need = int(_lib.lms_window_agg_multi_workspace(arr, len(bs), self.key_col, ctypes.byref(w), aa,
+                                                       len(self.aggs)))
+        if need == 0:
+            raise LmsError(LMS_EINVAL, last_error() or "invalid multi-batch job")
+        return need
+
+    def reserve(self, nbytes: int):
+        """Allocates the workspace up front (it cannot move once launches are frozen)."""
+        if self.launch_cfg is not None and nbytes > self.ws.numel():
+            raise LmsError(LMS_ENOMEM, "the workspace of a frozen job cannot grow")
+        if self.ws.numel() < nbytes:
+            self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def prepare(self, batches, groups=None, caps=None, d_counts=None, stream=None):
+        bs, arr, aa = self._arrays(batches)
+        w = self.window.c()
+        nb = len(bs)
+        self.reserve(self.workspace_bytes(batches))
+        if groups is None:
+            slide = self.window.slide or self.window.length
+            per = -(-self.window.length // slide)
+            caps = caps or [b.batch.nrows * per for b in bs]
+            groups = [Groups(c, self.aggs, self.device) for c in caps]
+        if d_counts is None:
+            d_counts = torch.zeros((nb, 2), dtype=torch.int64, device=self.device)
+        outs = (lms_groups * nb)(*[g.c for g in groups])
+        pa, npred = _preds(self.preds)
+        pr, nproj = _projs(self.projs)
+        _check(_lib.lms_window_agg_multi_prepare(arr, nb, pa, npred, pr, nproj, self.key_col, ctypes.byref(w), aa,
+                                                 len(self.aggs), outs, d_counts.data_ptr(), self.ws.data_ptr(),
+                                                 self.ws.numel(), ctypes.byref(self.cfg), _stream_handle(stream)))
+        self._keep = (bs, groups, d_counts)
+        self.groups, self.d_counts = groups, d_counts
+        return groups, d_counts
+
+    def launch(self, stream=None, cfg: lms_multi_config | None = None):
+        c = cfg or self.launch_cfg or self.cfg
+        _check(_lib.lms_window_agg_multi_launch(ctypes.byref(c), self.ws.data_ptr(), _stream_handle(stream)))
+
+    def freeze(self, max_nparts=None):
+        """Fixes the launch configuration and the workspace (as for graph capture) to
+        the prepared ones, or with room for up to ``max_nparts`` partitions per batch.
+        Later prepares must fit the workspace; jobs beyond the launch limits are
+        rejected by the kernels (status LMS_EINVAL)."""
+        c = lms_multi_config()
+        ctypes.pointer(c)[0] = self.cfg
+        if max_nparts:
+            c.max_nparts = max(c.max_nparts, max_nparts)
+        self.launch_cfg = c
+        return c
+
+
+def lms_window_agg_multi(batches, key_col, window: Window, aggs, preds=(), projs=(), stream=None):
+    """One-shot multi-batch windowed group-by; returns (list of Groups, d_counts[nb, 2])."""
+    job = MultiJob(key_col, window, aggs, preds, projs, device=batches[0][0].device)
+    g, d = job.prepare(batches, stream=stream)
+    job.launch(stream=stream)
+    return g, d, job
+
+
+def set_tuning(chunk_rows=0, part_rows=0, piece_rows=0, grid_per_cu=0):
+    t = lms_tuning(chunk_rows, part_rows, piece_rows, grid_per_cu)
+    _check(_lib.lms_set_tuning(ctypes.byref(t)))
+
+
+def get_tuning() -> dict:
+    t = lms_tuning()
+    _check(_lib.lms_get_tuning(ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in lms_tuning._fields_}
 
 
 # ---- stream-static join ------------------------------------------------------------------

@@ -224,6 +224,88 @@ typedef struct {
 int lms_set_tuning(const lms_tuning* t);
 int lms_get_tuning(lms_tuning* t);
 
+/* ---- Window state across micro-batches ----------------------------------------
+ * The windowed group-by of a stream that arrives as a sequence of
+ * micro-batches (Sec. II-A window semantics, Sec. III: every micro-batch is a
+ * query execution over the newly admitted datasets): partial aggregates of
+ * windows still open are kept on the device between micro-batches, per
+ * (key, pane) with pane = gcd(len, slide), and each window is emitted once,
+ * after the watermark passes its end.  The handle owns one device allocation
+ * of lms_wstate_bytes(max_keys, ring_panes, nagg) bytes (what a caller
+ * admitting work by free HBM reserves).
+ *
+ * lms_wstate_create: window (ts_col must be an int64 input column at update
+ *   time), aggregates as in lms_window_agg (SUM/MIN/MAX over integer columns,
+ *   AVG over any; columns index the update's inputs followed by its
+ *   projections), max_keys distinct keys over the stream's life (the key
+ *   dictionary never shrinks), ring_panes >= the panes between the oldest
+ *   window not yet emitted and the newest row (rounded up to a power of two,
+ *   at least len/pane + slide/pane).  Initialisation is enqueued on `stream`.
+ * lms_wstate_update: adds the passing rows of a micro-batch.  Rows whose pane
+ *   lies only in already-emitted windows are late: dropped and counted.  Rows
+ *   that find the dictionary full or their pane's ring entry held by another
+ *   live pane are dropped and counted, and set status LMS_ECAPACITY.
+ * lms_wstate_emit: writes every window not yet emitted whose end
+ *   (start + len) is <= watermark -- or, with flush != 0, every remaining
+ *   window holding data -- at most max_windows window starts per call, in
+ *   order; then clears the panes no later window needs.  Output as
+ *   lms_window_agg: d_count[0] = groups (written up to out->cap; more sets
+ *   d_count[1] = LMS_ECAPACITY).  Repeated flush calls drain the rest.
+ * lms_wstate_info: copies 8 int64 control words to device memory d_info:
+ *   late rows, capacity drops, min pane, max pane, next window index, last
+ *   emitted window range [lo, hi], status.
+ * Calls on one state must be ordered (one stream, or events); different
+ * states are independent. */
+typedef struct lms_wstate lms_wstate;
+size_t lms_wstate_bytes(int64_t max_keys, int32_t ring_panes, int32_t nagg);
+int lms_wstate_create(const lms_window* w, const lms_agg* aggs, int32_t nagg, int64_t max_keys, int32_t ring_panes,
+                      lms_wstate** out, lms_stream stream);
+int lms_wstate_update(lms_wstate* st, const lms_batch* in, const lms_pred* preds, int32_t npred,
+                      const lms_proj* projs, int32_t nproj, int32_t key_col, lms_stream stream);
+int lms_wstate_emit(lms_wstate* st, int64_t watermark, int32_t flush, int32_t max_windows, const lms_groups* out,
+                    int64_t* d_count, lms_stream stream);
+int lms_wstate_info(lms_wstate* st, int64_t* d_info, lms_stream stream);
+void lms_wstate_free(lms_wstate* st);
+
+/* ---- Micro-batch admission (ConstructMicroBatch) ---------------------------------
+ * Host-only controller of Algorithm 1: datasets arriving from the stream are
+ * buffered until the estimated maximum latency of the micro-batch they would
+ * form (Eq. 6: oldest buffering time + rows / AvgThPut of Eq. 4) plus one poll
+ * period reaches the deadline: SlideTime for sliding windows (Eq. 2), the
+ * mean MaxLat (Eq. 5) of the completed batches for tumbling ones (Eq. 3), or
+ * an explicit deadline.  The caller polls every poll_ms with the datasets that
+ * arrived since its last call and reports each finished batch with
+ * lms_admit_done.  Times are in ms on any one clock. */
+typedef struct {
+  double slide_ms;     /* SlideTime; 0 for a tumbling window */
+  double deadline_ms;  /* > 0: explicit latency bound, replacing the window rule */
+  double poll_ms;      /* polling period (10 ms in the paper) */
+  int32_t poll_idle;   /* 1: also test on polls without new data; 0: only when data arrived */
+  int32_t reserved;
+} lms_admit_params;
+typedef struct {
+  int32_t admit;             /* 1: the buffered datasets form the next micro-batch */
+  int32_t reserved;
+  int64_t datasets, rows;    /* size of the admitted micro-batch (0 if not admitted) */
+  double oldest_arrival_ms;  /* creation time of its oldest dataset */
+  double est_maxlat_ms;      /* EstMaxLat of the buffered datasets at this poll */
+  int64_t buffered_datasets, buffered_rows; /* buffer before the decision */
+} lms_admit_decision;
+typedef struct {
+  int64_t batches_done, admitted, rows_done, buffered_rows;
+  double avg_thput_rows_per_ms, mean_maxlat_ms;
+} lms_admit_stats;
+typedef struct lms_admit lms_admit;
+int lms_admit_create(const lms_admit_params* p, lms_admit** out);
+/* arrival_ms/rows: host arrays of the n_new datasets that arrived since the
+ * last poll (any order).  On admission the buffer is handed over whole, in
+ * creation order, and emptied. */
+int lms_admit_poll(lms_admit* a, double now_ms, int64_t n_new, const double* arrival_ms, const int64_t* rows,
+                   lms_admit_decision* out);
+int lms_admit_done(lms_admit* a, int64_t rows, double proc_ms, double maxlat_ms);
+int lms_admit_get_stats(const lms_admit* a, lms_admit_stats* out);
+void lms_admit_free(lms_admit* a);
+
 /* ---- Stream-static hash join (Table II "Join (Hash)"; the join of LR1 in
  * Table III) ---------------------------------------------------------------
  * lms_join_build hashes the static table `tbl` on integer column key_col and

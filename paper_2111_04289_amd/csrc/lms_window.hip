@@ -91,6 +91,10 @@ struct WinArgs {
   int64_t* d_count;
 };
 
+// LDS the multi-batch aggregation kernels keep for their copy of the batch
+// arguments (static LDS, ahead of the 16-byte-aligned dynamic part)
+constexpr int kArgsLds = (int)((sizeof(WinArgs) + 255) / 256 * 256);
+
 __device__ __forceinline__ int part_of(uint64_t h, int pbits) { return pbits ? (int)(h >> (64 - pbits)) : 0; }
 __device__ __forceinline__ uint32_t subhash(uint64_t h) { return (uint32_t)(h >> 16); }
 
@@ -313,7 +317,18 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
 template <int MA>
 __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
   extern __shared__ uint32_t cursor[];
-  scatter_chunk<MA>(a, blockIdx.x, cursor);
+  if constexpr (MA == 8) {
+    // at this unroll bound the loops over value columns stay rolled and would
+    // index the by-value arguments dynamically (a private-memory copy); an LDS
+    // copy avoids that
+    __shared__ WinArgs sa;
+    const uint32_t* src = (const uint32_t*)&a;
+    for (uint32_t i = threadIdx.x; i < sizeof(WinArgs) / 4; i += blockDim.x) ((uint32_t*)&sa)[i] = src[i];
+    __syncthreads();
+    scatter_chunk<MA>(sa, blockIdx.x, cursor);
+  } else {
+    scatter_chunk<MA>(a, blockIdx.x, cursor);
+  }
 }
 
 // LDS layout of one aggregation workgroup.
@@ -1140,7 +1155,7 @@ Plan make_plan(int64_t n, int nval, int nacc) {
   p.max_items = p.nparts + (int)((n + p.rs - 1) / p.rs);
   p.eg = 2048;
   p.ek = 1024;
-  while (lds_bytes(p.ek, p.eg, nacc) + sizeof(WinArgs) > (size_t)kLdsLimit && p.eg > 1024) {
+  while (lds_bytes(p.ek, p.eg, nacc) + kArgsLds > (size_t)kLdsLimit && p.eg > 1024) {
     p.eg /= 2;
     p.ek /= 2;
   }
@@ -1366,15 +1381,16 @@ size_t multi_desc_bytes(int nb) {
 }
 
 template <int MA>
-void launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
-  static bool attr_done = false;
-  if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)k_wam_agg<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kLdsLimit - (int)sizeof(WinArgs));
-    (void)hipFuncSetAttribute((const void*)k_wam_merge<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kLdsLimit - (int)sizeof(WinArgs));
-    attr_done = true;
-  }
+int launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
+  static const int attr_rc = [] {
+    int rc = check_hip(hipFuncSetAttribute((const void*)k_wam_agg<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsLimit - kArgsLds), "LDS attribute");
+    if (!rc)
+      rc = check_hip(hipFuncSetAttribute((const void*)k_wam_merge<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kLdsLimit - kArgsLds), "LDS attribute");
+    return rc;
+  }();
+  if (attr_rc) return attr_rc;
   const size_t plds = (size_t)c.max_nparts * 4;
   const MultiLim lim{(uint32_t)c.max_nparts, (uint32_t)c.agg_lds, (uint32_t)MA, 0};
   LMS_LAUNCH("k_wam_init", k_wam_init, dim3(4), dim3(256), 0, st, desc, lim);
@@ -1384,6 +1400,7 @@ void launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
   LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
   LMS_LAUNCH("k_wam_agg", k_wam_agg<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
   LMS_LAUNCH("k_wam_merge", k_wam_merge<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
+  return LMS_OK;
 }
 
 }  // namespace
@@ -1532,16 +1549,18 @@ extern "C" int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nb
 extern "C" int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lms_stream stream) {
   if (!cfg || !workspace || cfg->nbatch <= 0) return set_error(LMS_EINVAL, "bad multi-batch launch arguments");
   if (cfg->grid_scan <= 0 || cfg->grid_agg <= 0 || cfg->max_nparts <= 0 || cfg->max_nparts > 4096 ||
-      cfg->agg_lds > (uint64_t)(kLdsLimit - (int)sizeof(WinArgs)) ||
+      cfg->agg_lds > (uint64_t)(kLdsLimit - kArgsLds) ||
       !(cfg->ma == 2 || cfg->ma == 4 || cfg->ma == 6 || cfg->ma == 8))
     return set_error(LMS_EINVAL, "bad multi-batch configuration");
   hipStream_t st = (hipStream_t)stream;
   const char* desc = (const char*)workspace;
+  int rc = LMS_OK;
   switch (cfg->ma) {
-    case 2: launch_multi<2>(*cfg, desc, st); break;
-    case 4: launch_multi<4>(*cfg, desc, st); break;
-    case 6: launch_multi<6>(*cfg, desc, st); break;
-    case 8: launch_multi<8>(*cfg, desc, st); break;
+    case 2: rc = launch_multi<2>(*cfg, desc, st); break;
+    case 4: rc = launch_multi<4>(*cfg, desc, st); break;
+    case 6: rc = launch_multi<6>(*cfg, desc, st); break;
+    case 8: rc = launch_multi<8>(*cfg, desc, st); break;
   }
+  if (rc) return rc;
   return check_hip(hipGetLastError(), "multi-batch launch");
 }

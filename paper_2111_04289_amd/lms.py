@@ -106,6 +106,23 @@ class lms_multi_config(ctypes.Structure):
                 ("agg_lds", ctypes.c_uint64)]
 
 
+class lms_admit_params(ctypes.Structure):
+    _fields_ = [("slide_ms", ctypes.c_double), ("deadline_ms", ctypes.c_double), ("poll_ms", ctypes.c_double),
+                ("poll_idle", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lms_admit_decision(ctypes.Structure):
+    _fields_ = [("admit", ctypes.c_int32), ("reserved", ctypes.c_int32), ("datasets", ctypes.c_int64),
+                ("rows", ctypes.c_int64), ("oldest_arrival_ms", ctypes.c_double), ("est_maxlat_ms", ctypes.c_double),
+                ("buffered_datasets", ctypes.c_int64), ("buffered_rows", ctypes.c_int64)]
+
+
+class lms_admit_stats(ctypes.Structure):
+    _fields_ = [("batches_done", ctypes.c_int64), ("admitted", ctypes.c_int64), ("rows_done", ctypes.c_int64),
+                ("buffered_rows", ctypes.c_int64), ("avg_thput_rows_per_ms", ctypes.c_double),
+                ("mean_maxlat_ms", ctypes.c_double)]
+
+
 class lms_tuning(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int32), ("part_rows", ctypes.c_int32), ("piece_rows", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32)]
@@ -128,6 +145,17 @@ _SIGS = {
                                                     _P(lms_window), _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz,
                                                     _P(lms_multi_config), _vp]),
     "lms_window_agg_multi_launch": (ctypes.c_int, [_P(lms_multi_config), _vp, _vp]),
+    "lms_wstate_bytes": (_sz, [_i64, _i32, _i32]),
+    "lms_wstate_create": (ctypes.c_int, [_P(lms_window), _P(lms_agg), _i32, _i64, _i32, _P(_vp), _vp]),
+    "lms_wstate_update": (ctypes.c_int, [_vp, _P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _i32, _vp]),
+    "lms_wstate_emit": (ctypes.c_int, [_vp, _i64, _i32, _i32, _P(lms_groups), _vp, _vp]),
+    "lms_wstate_info": (ctypes.c_int, [_vp, _vp, _vp]),
+    "lms_wstate_free": (None, [_vp]),
+    "lms_admit_create": (ctypes.c_int, [_P(lms_admit_params), _P(_vp)]),
+    "lms_admit_poll": (ctypes.c_int, [_vp, ctypes.c_double, _i64, _vp, _vp, _P(lms_admit_decision)]),
+    "lms_admit_done": (ctypes.c_int, [_vp, _i64, ctypes.c_double, ctypes.c_double]),
+    "lms_admit_get_stats": (ctypes.c_int, [_vp, _P(lms_admit_stats)]),
+    "lms_admit_free": (None, [_vp]),
     "lms_set_tuning": (ctypes.c_int, [_P(lms_tuning)]),
     "lms_get_tuning": (ctypes.c_int, [_P(lms_tuning)]),
     "lms_join_build": (ctypes.c_int, [_P(lms_batch), _i32, _i32, _P(_vp), _vp]),
@@ -421,6 +449,101 @@ def lms_window_agg_multi(batches, key_col, window: Window, aggs, preds=(), projs
     g, d = job.prepare(batches, stream=stream)
     job.launch(stream=stream)
     return g, d, job
+
+
+class WindowState:
+    """Device-resident partial aggregates of a windowed group-by over a stream of
+    micro-batches (lms_wstate_*): ``update`` adds a batch, ``emit`` writes the
+    windows the watermark has closed (all remaining ones with ``flush``)."""
+
+    INFO = ("late_rows", "dropped_rows", "min_pane", "max_pane", "next_window", "emit_lo", "emit_hi", "status")
+
+    def __init__(self, window: Window, aggs, max_keys: int, ring_panes: int = 32, device=None, stream=None):
+        self.window, self.aggs = window, list(aggs)
+        self.device = device or torch.device("cuda")
+        aa = (lms_agg * max(1, len(self.aggs)))(*[lms_agg(f, c) for f, c in self.aggs])
+        w = window.c()
+        h = ctypes.c_void_p()
+        _check(_lib.lms_wstate_create(ctypes.byref(w), aa, len(self.aggs), max_keys, ring_panes, ctypes.byref(h),
+                                      _stream_handle(stream)))
+        self.handle = h
+        self.nbytes = int(_lib.lms_wstate_bytes(max_keys, ring_panes, len(self.aggs)))
+        self._info = torch.zeros(8, dtype=torch.int64, device=self.device)
+
+    @staticmethod
+    def bytes(max_keys: int, ring_panes: int, nagg: int) -> int:
+        return int(_lib.lms_wstate_bytes(max_keys, ring_panes, nagg))
+
+    def update(self, cols, key_col, preds=(), projs=(), stream=None):
+        b = _Batch(cols)
+        pa, npred = _preds(preds)
+        pr, nproj = _projs(projs)
+        _check(_lib.lms_wstate_update(self.handle, ctypes.byref(b.batch), pa, npred, pr, nproj, key_col,
+                                      _stream_handle(stream)))
+        return b  # keeps the column array alive until the caller drops it
+
+    def emit(self, watermark: int = 0, flush: bool = False, max_windows: int = 1 << 20, groups=None, cap=None,
+             d_count=None, stream=None):
+        if groups is None:
+            groups = Groups(cap if cap is not None else 1 << 16, self.aggs, self.device)
+        if d_count is None:
+            d_count = torch.zeros(2, dtype=torch.int64, device=self.device)
+        _check(_lib.lms_wstate_emit(self.handle, int(watermark), int(bool(flush)), int(max_windows),
+                                    ctypes.byref(groups.c), d_count.data_ptr(), _stream_handle(stream)))
+        return groups, d_count
+
+    def info(self, stream=None) -> dict:
+        _check(_lib.lms_wstate_info(self.handle, self._info.data_ptr(), _stream_handle(stream)))
+        return dict(zip(self.INFO, (int(x) for x in self._info.cpu())))
+
+    def free(self):
+        if self.handle:
+            _lib.lms_wstate_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Admission:
+    """ConstructMicroBatch (lms_admit_*): buffers arriving datasets and decides at
+    each poll whether they form the next micro-batch."""
+
+    def __init__(self, slide_ms=0.0, deadline_ms=0.0, poll_ms=10.0, poll_idle=True):
+        p = lms_admit_params(float(slide_ms), float(deadline_ms), float(poll_ms), int(bool(poll_idle)), 0)
+        h = ctypes.c_void_p()
+        _check(_lib.lms_admit_create(ctypes.byref(p), ctypes.byref(h)))
+        self.handle = h
+        self._d = lms_admit_decision()
+
+    def poll(self, now_ms, arrival_ms=(), rows=()) -> lms_admit_decision:
+        import numpy as np
+        a = np.ascontiguousarray(arrival_ms, dtype=np.float64)
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        if len(a) != len(r):
+            raise ValueError("arrival_ms and rows differ in length")
+        _check(_lib.lms_admit_poll(self.handle, float(now_ms), len(a), a.ctypes.data, r.ctypes.data,
+                                   ctypes.byref(self._d)))
+        return self._d
+
+    def done(self, rows, proc_ms, maxlat_ms):
+        _check(_lib.lms_admit_done(self.handle, int(rows), float(proc_ms), float(maxlat_ms)))
+
+    def stats(self) -> dict:
+        st = lms_admit_stats()
+        _check(_lib.lms_admit_get_stats(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in lms_admit_stats._fields_}
+
+    def __del__(self):
+        try:
+            if self.handle:
+                _lib.lms_admit_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
 
 
 def set_tuning(chunk_rows=0, part_rows=0, piece_rows=0, grid_per_cu=0):

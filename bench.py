@@ -46,7 +46,31 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-stream comparison")
     ap.add_argument("--batches", type=int, default=256)
     ap.add_argument("--tuning", default=None, help="tuning JSON written by the autotuner (default: the packaged one)")
+    ap.add_argument("--serve-step-s", type=float, default=3.0,
+                    help="seconds per rate step of the serving comparison (0 skips it)")
     return ap.parse_args()
+
+
+def run_serving(args, log):
+    """The served form (admission per query, continuous batching, learned
+    placement when a trained model is packaged) against the plain fixed-trigger
+    form on the same Poisson stream (rates 0.1, 1, 5, 10 M rows/s)."""
+    from paper_2111_04289_amd import placement, serve
+    model = placement.load_model()
+    out = {"step_s": args.serve_step_s, "placement": "learned" if model is not None else "analytic"}
+    t = serve.Traffic((0.1e6, 1e6, 5e6, 10e6), args.serve_step_s)
+    arr = t.arrivals_ms()
+    data = serve.StreamData(arr, 1 << 24)
+    for mode in ("served", "baseline"):
+        eng = serve.Engine(data, mode=mode, model=model, log=log)
+        res = eng.run()
+        out[mode] = {k: res[k] for k in ("p50_ms", "p99_ms", "Mrows_s", "wall_s", "hbm_waits")}
+        out[mode]["queries"] = {q: {k: v[k] for k in ("p50_ms", "p99_ms", "maxlat_p99_ms", "batches", "cpu_batches")}
+                                for q, v in res["queries"].items()}
+        log(f"serving {mode}: {json.dumps(res)}")
+        del eng
+    out["stream_rows"] = int(len(arr) * serve.DS_ROWS)
+    return out
 
 
 def run_batched(args, torch, lms, datagen, cols, dev):
@@ -241,6 +265,11 @@ def main():
     for k, v in sorted(trace.items(), key=lambda kv: -kv[1][1]):
         log(f"{k:14s} launches {v[0]:4d} avg {v[1] / v[0]:.4f} ms  min {v[2]:.4f}  max {v[3]:.4f}")
 
+    del groups, fp_out, j_idx, j_pay
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    serving = run_serving(args, log) if args.serve_step_s > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -286,6 +315,7 @@ def main():
         "window_status": status,
         "tuning": tuned,
         "batched": batched,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -214,12 +214,17 @@ int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lm
 /* Tile and schedule parameters of the windowed group-by (process-wide; NULL
  * or 0 fields select the defaults): rows per scan chunk, target rows per
  * partition, rows per aggregation piece (>= 1024), persistent scan workgroups
- * per CU.  Chosen by the project's autotuner. */
+ * per CU, and (key, pane) slots of an aggregation workgroup's LDS table (a
+ * power of two in [256, 2048]; smaller tables let two workgroups share a CU
+ * and lower the panes one key may hold, lms_window_agg_pane_limit).  Chosen
+ * by the project's autotuner; results never depend on them. */
 typedef struct {
   int32_t chunk_rows;
   int32_t part_rows;
   int32_t piece_rows;
   int32_t grid_per_cu;
+  int32_t lds_groups;
+  int32_t reserved;
 } lms_tuning;
 int lms_set_tuning(const lms_tuning* t);
 int lms_get_tuning(lms_tuning* t);

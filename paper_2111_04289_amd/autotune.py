@@ -1,9 +1,11 @@
 """Autotuner of the windowed group-by's tile and schedule parameters.
 
 The parameters (``lms_tuning``: rows per scan chunk, target rows per hash
-partition, rows per aggregation piece, persistent scan workgroups per CU) trade
-parallelism against per-workgroup overhead and L2 locality; the best values
-depend on the batch-size mix.  ``tune`` searches them by coordinate descent on
+partition, rows per aggregation piece, persistent scan workgroups per CU, LDS
+group-table slots per aggregation workgroup) trade parallelism and occupancy
+against per-workgroup overhead and L2 locality; the best values depend on the
+batch-size mix.  A candidate whose run reports a nonzero device status is
+discarded.  ``tune`` searches them by coordinate descent on
 a workload timed on the GPU (each parameter swept with the others fixed, two
 passes) and writes the winners per workload to JSON; ``apply`` loads them into
 the library before a run.  Every candidate runs the same kernels, so results
@@ -31,6 +33,7 @@ SPACE = {
     "part_rows": [0, 8192, 32768],
     "piece_rows": [0, 4096, 16384],
     "grid_per_cu": [0, 2, 8],
+    "lds_groups": [0, 1024, 512],
 }
 DEFAULT = {k: 0 for k in SPACE}
 
@@ -63,7 +66,10 @@ def _sliding(torch, dev, rows):
     def run():
         lms.lms_window_agg(cols, 1, w, aggs, preds, groups=groups, d_count=cnt, workspace=ws)
 
-    return run
+    def ok():
+        return int(cnt[1]) == 0
+
+    return run, ok
 
 
 def _batched(torch, dev, rows, nbatch=256, seed=11):
@@ -85,7 +91,10 @@ def _batched(torch, dev, rows, nbatch=256, seed=11):
             state["tuning"] = lms.get_tuning()
         job.launch()
 
-    return run
+    def ok():
+        return not bool(state["cnt"][:, 1].any())
+
+    return run, ok
 
 
 WORKLOADS = {"sliding": _sliding, "batched": _batched}
@@ -106,10 +115,12 @@ def _time(torch, run, reps):
 def tune(workload: str, rows: int = 1 << 24, reps: int = 5, passes: int = 2, log=print):
     import torch
     dev = torch.device("cuda:0")
-    run = WORKLOADS[workload](torch, dev, rows)
+    run, ok = WORKLOADS[workload](torch, dev, rows)
     best = dict(DEFAULT)
     lms.set_tuning(**best)
     best_ms = _time(torch, run, reps)
+    if not ok():
+        raise RuntimeError(f"{workload}: the default tuning reports a device status")
     base_ms = best_ms
     tried = {tuple(best.values()): best_ms}
     log(f"{workload}: default {best_ms:.4f} ms")
@@ -122,6 +133,8 @@ def tune(workload: str, rows: int = 1 << 24, reps: int = 5, passes: int = 2, log
                 if key not in tried:
                     lms.set_tuning(**cand)
                     tried[key] = _time(torch, run, reps)
+                    if not ok():
+                        tried[key] = float("inf")
                     log(f"{workload}: {cand} {tried[key]:.4f} ms")
                 if tried[key] < best_ms * 0.99:
                     best, best_ms, changed = cand, tried[key], True

@@ -1140,7 +1140,7 @@ int64_t gcd64(int64_t x, int64_t y) {
   return x;
 }
 
-lms_tuning g_tuning{0, 0, 0, 0};
+lms_tuning g_tuning{0, 0, 0, 0, 0, 0};
 
 Plan make_plan(int64_t n, int nval, int nacc) {
   Plan p{};
@@ -1153,8 +1153,8 @@ Plan make_plan(int64_t n, int nval, int nacc) {
   p.pbits = ilog2(p.nparts);
   p.rs = g_tuning.piece_rows > 0 ? g_tuning.piece_rows : 8192;
   p.max_items = p.nparts + (int)((n + p.rs - 1) / p.rs);
-  p.eg = 2048;
-  p.ek = 1024;
+  p.eg = g_tuning.lds_groups > 0 ? g_tuning.lds_groups : 2048;
+  p.ek = p.eg / 2;
   while (lds_bytes(p.ek, p.eg, nacc) + kArgsLds > (size_t)kLdsLimit && p.eg > 1024) {
     p.eg /= 2;
     p.ek /= 2;
@@ -1432,12 +1432,14 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
 
 extern "C" int lms_set_tuning(const lms_tuning* t) {
   if (!t) {
-    g_tuning = lms_tuning{0, 0, 0, 0};
+    g_tuning = lms_tuning{0, 0, 0, 0, 0, 0};
     return LMS_OK;
   }
-  if (t->chunk_rows < 0 || t->part_rows < 0 || t->piece_rows < 0 || t->grid_per_cu < 0)
+  if (t->chunk_rows < 0 || t->part_rows < 0 || t->piece_rows < 0 || t->grid_per_cu < 0 || t->lds_groups < 0)
     return set_error(LMS_EINVAL, "tuning values must be >= 0");
   if (t->piece_rows > 0 && t->piece_rows < 1024) return set_error(LMS_EINVAL, "piece_rows must be >= 1024");
+  if (t->lds_groups != 0 && (t->lds_groups < 256 || t->lds_groups > 2048 || (t->lds_groups & (t->lds_groups - 1))))
+    return set_error(LMS_EINVAL, "lds_groups must be 0 or a power of two in [256, 2048]");
   g_tuning = *t;
   return LMS_OK;
 }

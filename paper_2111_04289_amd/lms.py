@@ -125,7 +125,7 @@ class lms_admit_stats(ctypes.Structure):
 
 class lms_tuning(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int32), ("part_rows", ctypes.c_int32), ("piece_rows", ctypes.c_int32),
-                ("grid_per_cu", ctypes.c_int32)]
+                ("grid_per_cu", ctypes.c_int32), ("lds_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -546,15 +546,15 @@ class Admission:
             pass
 
 
-def set_tuning(chunk_rows=0, part_rows=0, piece_rows=0, grid_per_cu=0):
-    t = lms_tuning(chunk_rows, part_rows, piece_rows, grid_per_cu)
+def set_tuning(chunk_rows=0, part_rows=0, piece_rows=0, grid_per_cu=0, lds_groups=0):
+    t = lms_tuning(chunk_rows, part_rows, piece_rows, grid_per_cu, lds_groups, 0)
     _check(_lib.lms_set_tuning(ctypes.byref(t)))
 
 
 def get_tuning() -> dict:
     t = lms_tuning()
     _check(_lib.lms_get_tuning(ctypes.byref(t)))
-    return {f: getattr(t, f) for f, _ in lms_tuning._fields_}
+    return {f: getattr(t, f) for f, _ in lms_tuning._fields_ if f != "reserved"}
 
 
 # ---- stream-static join ------------------------------------------------------------------

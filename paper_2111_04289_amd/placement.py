@@ -32,7 +32,18 @@ import torch
 
 from . import datagen, lms
 
+MODEL_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "placement_mlp.npy")
+
 OPS = ("fp", "tumble", "slide", "join")
+
+
+def load_model(path: str | None = None):
+    """The packaged trained parameters (float32), or None if there are none."""
+    path = path or MODEL_PATH
+    if not os.path.exists(path):
+        return None
+    p = np.load(path).astype(np.float32)
+    return p if p.size == lms.MLP_NPARAMS else None
 KIND = {"fp": lms.OP_FILTER, "tumble": lms.OP_AGG, "slide": lms.OP_AGG, "join": lms.OP_JOIN}
 WINDOWS = ((10, 1), (30, 5), (30, 10), (60, 10), (60, 5))  # range/slide shapes of the paper's queries (s)
 COLS_READ = {"fp": 3, "tumble": 4, "slide": 4, "join": 1}

@@ -124,7 +124,8 @@ def test_multi_graph_replay(lms):
     assert int(d3[0][1]) == lms.LMS_EINVAL and int(d3[0][0]) == 0
 
 
-@pytest.mark.parametrize("tuning", [dict(chunk_rows=2048, part_rows=8192, piece_rows=1024, grid_per_cu=1),
+@pytest.mark.parametrize("tuning", [dict(chunk_rows=2048, part_rows=8192, piece_rows=1024, grid_per_cu=1,
+                                         lds_groups=512),
                                     dict(chunk_rows=65536, part_rows=65536, piece_rows=32768, grid_per_cu=8)])
 def test_tuning_keeps_results(lms, tuning):
     """Tile and schedule parameters change the work split, never the result."""

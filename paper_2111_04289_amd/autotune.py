@@ -6,8 +6,8 @@ group-table slots per aggregation workgroup) trade parallelism and occupancy
 against per-workgroup overhead and L2 locality; the best values depend on the
 batch-size mix.  A candidate whose run reports a nonzero device status is
 discarded.  ``tune`` searches them by coordinate descent on
-a workload timed on the GPU (each parameter swept with the others fixed, two
-passes) and writes the winners per workload to JSON; ``apply`` loads them into
+a workload timed on the GPU (each coordinate swept with the others fixed, up
+to two passes) and writes the winners per workload to JSON; ``apply`` loads them into
 the library before a run.  Every candidate runs the same kernels, so results
 do not depend on the tuning (the GPU tests check a non-default setting against
 the oracle).
@@ -30,12 +30,20 @@ PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json"
 
 SPACE = {
     "chunk_rows": [0, 2048, 8192, 32768, 65536],
-    "part_rows": [0, 8192, 32768],
+    "part_rows": [0, 4096, 8192, 32768],
     "piece_rows": [0, 4096, 16384],
     "grid_per_cu": [0, 2, 8],
     "lds_groups": [0, 1024, 512],
 }
+# Coordinates of the descent; partition size and LDS table size move together
+# (a smaller table only pays off with smaller partitions).
+COORDS = [("chunk_rows",), ("part_rows", "lds_groups"), ("piece_rows",), ("grid_per_cu",)]
 DEFAULT = {k: 0 for k in SPACE}
+
+
+def _values(coord):
+    import itertools
+    return list(itertools.product(*(SPACE[name] for name in coord)))
 
 
 def apply(workload: str, path: str | None = None):
@@ -126,9 +134,9 @@ def tune(workload: str, rows: int = 1 << 24, reps: int = 5, passes: int = 2, log
     log(f"{workload}: default {best_ms:.4f} ms")
     for _ in range(passes):
         changed = False
-        for name, values in SPACE.items():
-            for v in values:
-                cand = dict(best, **{name: v})
+        for coord in COORDS:
+            for v in _values(coord):
+                cand = dict(best, **dict(zip(coord, v)))
                 key = tuple(cand.values())
                 if key not in tried:
                     lms.set_tuning(**cand)

@@ -6,11 +6,14 @@
 // with one 32-bit CAS, duplicate keys take separate slots.  All slots of a key
 // lie in the run of used slots that starts at its home slot, so a probe walks
 // from the home slot to the first unused slot.
-// Probe: per-tile match counts, a scan of the tile counts, then a write pass
-// that ranks each round of rows with a block prefix, so the pairs come out
-// grouped by ascending probe row without global atomics.  Each thread walks
-// the chains of several consecutive rows in lockstep to overlap the random
-// slot reads (the table is MALL-resident, not L2-resident).
+// Probe: one pass walks the chains and records each row's match count and
+// first payload (8 bytes per row, coalesced) with per-tile totals; a scan of
+// the tile counts; then a write pass that ranks each round of rows with a
+// block prefix, so the pairs come out grouped by ascending probe row without
+// global atomics, and touches the table again only for rows with several
+// matches.  Each thread walks the chains of several consecutive rows in
+// lockstep to overlap the random slot reads (the table is MALL-resident, not
+// L2-resident).
 #include <algorithm>
 
 #include "lms_internal.h"
@@ -36,7 +39,6 @@ namespace {
 constexpr int kTPB = 256;
 constexpr int kScanThreads = 1024;
 constexpr int kProbe = 4;  // probe rows per thread per round
-constexpr int kHold = 2;   // matches per row held in registers
 
 __global__ void k_jb_clear(JSlot* slots, uint64_t nslots, int64_t* d_mult) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -93,6 +95,7 @@ struct ProbeArgs {
   int64_t n;
   int64_t chunk;
   int32_t ntiles;
+  uint64_t* hits;  // per probe row: match count << 32 | first payload
   int64_t* tile_cnt;
   int64_t* tile_off;
   uint32_t* out_idx;
@@ -102,8 +105,8 @@ struct ProbeArgs {
 };
 
 // Walks the probe chains of kProbe consecutive rows in lockstep, so their slot
-// loads are independent; calls hit(u, payload) for every match of row u and
-// holds at most kHold payloads per row for the caller.
+// loads are independent; calls hit(u, payload) for every match of row u, in
+// chain order.
 template <class F>
 __device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)[kProbe], const bool (&valid)[kProbe],
                                           F hit) {
@@ -135,7 +138,10 @@ __device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)
   }
 }
 
-__global__ __launch_bounds__(kTPB) void k_jp_count(ProbeArgs a) {
+// Probe pass: walks every row's chain once and records, per row, its match
+// count and first payload (packed count << 32 | payload) for the write pass,
+// plus the tile's total.
+__global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
   __shared__ uint32_t scratch[kTPB / 64 + 1];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
@@ -143,12 +149,24 @@ __global__ __launch_bounds__(kTPB) void k_jp_count(ProbeArgs a) {
   for (int64_t b = lo + (int64_t)threadIdx.x * kProbe; b < hi; b += (int64_t)kTPB * kProbe) {
     int64_t k[kProbe];
     bool valid[kProbe];
+    uint32_t cnt[kProbe];
+    uint32_t first[kProbe];
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
       valid[u] = b + u < hi;
       k[u] = valid[u] ? load_i64(a.pkey, a.kdt, b + u) : 0;
+      cnt[u] = 0;
+      first[u] = 0;
     }
-    walk_rows(a, k, valid, [&](int, int32_t) { ++c; });
+    walk_rows(a, k, valid, [&](int u, int32_t pay) {
+      if (cnt[u] == 0) first[u] = (uint32_t)pay;
+      ++cnt[u];
+    });
+#pragma unroll
+    for (int u = 0; u < kProbe; ++u) {
+      if (valid[u]) a.hits[b + u] = ((uint64_t)cnt[u] << 32) | first[u];
+      c += cnt[u];
+    }
   }
   c = block_sum<kTPB>(c, scratch);
   if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = c;
@@ -164,6 +182,10 @@ __global__ __launch_bounds__(kScanThreads) void k_jp_scan(ProbeArgs a) {
   }
 }
 
+// Write pass: reads the recorded hits (no table access for rows with at most
+// one match), ranks each round of rows with a block prefix from the tile's
+// offset, and writes the pairs grouped by ascending probe row; a row with
+// several matches walks its chain again, in the same order.
 __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
   __shared__ uint32_t scratch[kTPB / 64 + 1];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
@@ -171,47 +193,31 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
   int64_t run = a.tile_off[blockIdx.x];
   for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kProbe) {
     const int64_t b = b0 + (int64_t)threadIdx.x * kProbe;
-    int64_t k[kProbe];
-    bool valid[kProbe];
-    uint32_t cnt[kProbe];
-    int32_t held[kProbe][kHold];
+    uint64_t h[kProbe];
 #pragma unroll
-    for (int u = 0; u < kProbe; ++u) {
-      valid[u] = b + u < hi;
-      k[u] = valid[u] ? load_i64(a.pkey, a.kdt, b + u) : 0;
-      cnt[u] = 0;
-#pragma unroll
-      for (int h = 0; h < kHold; ++h) held[u][h] = 0;
-    }
-    walk_rows(a, k, valid, [&](int u, int32_t pay) {
-#pragma unroll
-      for (int h = 0; h < kHold; ++h)
-        if (cnt[u] == (uint32_t)h) held[u][h] = pay;
-      ++cnt[u];
-    });
+    for (int u = 0; u < kProbe; ++u) h[u] = b + u < hi ? a.hits[b + u] : 0;
     uint32_t c = 0;
 #pragma unroll
-    for (int u = 0; u < kProbe; ++u) c += cnt[u];
+    for (int u = 0; u < kProbe; ++u) c += (uint32_t)(h[u] >> 32);
     uint32_t tot;
     int64_t o = run + block_excl_scan<kTPB>(c, scratch, &tot);
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
-      if (cnt[u] == 0) continue;
-      if (cnt[u] <= (uint32_t)kHold) {
-#pragma unroll
-        for (int h = 0; h < kHold; ++h) {
-          if ((uint32_t)h < cnt[u] && o + h < a.cap) {
-            a.out_idx[o + h] = (uint32_t)(b + u);
-            a.out_pay[o + h] = held[u][h];
-          }
+      const uint32_t cu = (uint32_t)(h[u] >> 32);
+      if (cu == 0) continue;
+      if (cu == 1) {
+        if (o < a.cap) {
+          a.out_idx[o] = (uint32_t)(b + u);
+          a.out_pay[o] = (int32_t)(uint32_t)h[u];
         }
-      } else {  // more matches than held: walk this row's chain again
+      } else {
+        const int64_t k = load_i64(a.pkey, a.kdt, b + u);
         int64_t r = o;
-        uint64_t s = fmix64((uint64_t)k[u]) & a.mask;
+        uint64_t s = fmix64((uint64_t)k) & a.mask;
         for (uint64_t t = 0; t <= a.mask; ++t) {
           const JSlot sl = a.slots[s];
           if (!sl.used) break;
-          if (sl.key == k[u]) {
+          if (sl.key == k) {
             if (r < a.cap) {
               a.out_idx[r] = (uint32_t)(b + u);
               a.out_pay[r] = sl.pay;
@@ -221,7 +227,7 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
           s = (s + 1) & a.mask;
         }
       }
-      o += cnt[u];
+      o += cu;
     }
     run += tot;
   }
@@ -252,9 +258,11 @@ size_t jp_workspace(int64_t n, ProbeArgs* a, void* base) {
   WsCarver c(base);
   int64_t* cnt = c.take<int64_t>(std::max(1, p.ntiles));
   int64_t* off = c.take<int64_t>(std::max(1, p.ntiles));
+  uint64_t* hits = c.take<uint64_t>(std::max<int64_t>(1, n));
   if (a) {
     a->tile_cnt = cnt;
     a->tile_off = off;
+    a->hits = hits;
   }
   return c.size();
 }
@@ -377,7 +385,7 @@ extern "C" int lms_hash_join(const lms_join_table* t, const lms_batch* probe, in
   if (probe->nrows == 0) {
     LMS_LAUNCH("k_jp_empty", k_jp_empty, dim3(1), dim3(64), 0, st, d_count);
   } else {
-    LMS_LAUNCH("k_jp_count", k_jp_count, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+    LMS_LAUNCH("k_jp_probe", k_jp_probe, dim3(p.ntiles), dim3(kTPB), 0, st, a);
     LMS_LAUNCH("k_jp_scan", k_jp_scan, dim3(1), dim3(kScanThreads), 0, st, a);
     LMS_LAUNCH("k_jp_write", k_jp_write, dim3(p.ntiles), dim3(kTPB), 0, st, a);
   }

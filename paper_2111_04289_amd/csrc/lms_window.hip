@@ -184,23 +184,102 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan1(WinArgs a) {
   scan1_part(a, blockIdx.x, scratch);
 }
 
-// Partition starts, per-(partition, chunk) write offsets and the work items of
-// the aggregation (a partition of R rows gives ceil(R / rs) items).
-__device__ void scan2_part(const WinArgs& a, int p, uint32_t* scratch) {
-  uint32_t s_rows = 0, s_items = 0;
-  for (int q = threadIdx.x; q < p; q += kScanTPB) {
-    const uint32_t r = a.Rp[q];
-    s_rows += r;
-    s_items += (uint32_t)((r + a.rs - 1) / a.rs);
+constexpr int kMaxParts = 4096;  // partitions of one batch (make_plan's bound)
+
+// Partition starts and the aggregation work items of one batch (one
+// workgroup; r, st, kc, base are kMaxParts-word LDS arrays):
+//  * a partition of more than rs rows gives ceil(R / rs) pieces, whose partial
+//    records k_wa_merge combines;
+//  * a partition of (rs/2, rs] rows is one item;
+//  * non-empty partitions of at most rs/2 rows are packed: consecutive ones
+//    whose starts fall in the same rs/2-row bucket form one item of at most
+//    rs rows (a larger partition between two of them always starts a new
+//    bucket), so low selectivity or small batches give few, fuller items.
+__device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t* kc, uint32_t* base,
+                           uint32_t* scratch) {
+  const int np = a.nparts;
+  const uint32_t rs = (uint32_t)a.rs, half = rs / 2;
+  for (int p = threadIdx.x; p < np; p += kScanTPB) {
+    const uint32_t v = a.Rp[p];
+    r[p] = v;
+    st[p] = v;
   }
-  const uint32_t start = block_sum<kScanTPB>(s_rows, scratch);
-  const uint32_t ibase = block_sum<kScanTPB>(s_items, scratch);
-  const uint32_t rp = a.Rp[p];
-  const uint32_t kp = (uint32_t)((rp + a.rs - 1) / a.rs);
-  // exclusive scan of H[p][*] over the chunks, in XCD-major order: workgroups
-  // are dispatched round-robin over the 8 XCDs, so chunks w, w+8, w+16, ...
-  // run on one XCD at about the same time; placing their segments next to each
-  // other lets that XCD's L2 merge the partial lines they write.
+  __syncthreads();
+  const uint32_t total = block_scan_array<kScanTPB>(st, np, scratch);
+  for (int p = threadIdx.x; p < np; p += kScanTPB) {
+    const uint32_t v = r[p];
+    uint32_t k = 0;
+    if (v > rs) {
+      k = (v + rs - 1) / rs;
+    } else if (v > half) {
+      k = 1;
+    } else if (v > 0) {  // packed: the first of its bucket leads the item
+      const uint32_t b = st[p] / half;
+      bool leader = true;
+      for (int q = p - 1; q >= 0; --q) {
+        const uint32_t w = r[q];
+        if (w == 0) continue;
+        leader = w > half || st[q] / half != b;
+        break;
+      }
+      k = leader ? 1 : 0;
+    }
+    kc[p] = k;
+    base[p] = k;
+  }
+  __syncthreads();
+  const uint32_t nitems = block_scan_array<kScanTPB>(base, np, scratch);
+  for (int p = threadIdx.x; p < np; p += kScanTPB) {
+    const uint32_t v = r[p], k = kc[p], ib = base[p], s0 = st[p];
+    if (k > 0) {
+      Item it;
+      it.p = p;
+      it.first = ib;
+      it.reserved[0] = it.reserved[1] = it.reserved[2] = 0;
+      if (v > rs) {
+        it.kp = k;
+        for (uint32_t j = 0; j < k; ++j) {
+          it.lo = s0 + j * rs;
+          it.hi = min(s0 + v, it.lo + rs);
+          a.items[ib + j] = it;
+        }
+      } else {
+        uint32_t hi = s0 + v;
+        if (v <= half) {  // extend over the rest of the bucket
+          const uint32_t b = s0 / half;
+          int q = p + 1;
+          while (q < np && (r[q] == 0 || (r[q] <= half && st[q] / half == b))) ++q;
+          hi = q < np ? st[q] : total;
+        }
+        it.kp = 1;
+        it.lo = s0;
+        it.hi = hi;
+        a.items[ib] = it;
+      }
+    }
+    a.pinfo[p].first = ib;
+    a.pinfo[p].kp = k;
+    a.pinfo[p].start = s0;
+    a.pinfo[p].reserved = 0;
+    a.pfill[p] = 0;
+  }
+  if (threadIdx.x == 0) a.hdr[1] = nitems;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kScanTPB) void k_wa_scanp(WinArgs a) {
+  __shared__ uint32_t r[kMaxParts], st[kMaxParts], kc[kMaxParts], base[kMaxParts];
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  plan_items(a, r, st, kc, base, scratch);
+}
+
+// Per-(partition, chunk) write offsets: partition start plus an exclusive scan
+// of H[p][*] over the chunks, in XCD-major order: workgroups are dispatched
+// round-robin over the 8 XCDs, so chunks w, w+8, w+16, ... run on one XCD at
+// about the same time; placing their segments next to each other lets that
+// XCD's L2 merge the partial lines they write.
+__device__ void scan2_part(const WinArgs& a, int p, uint32_t* scratch) {
+  const uint32_t start = a.pinfo[p].start;
   const int c8 = (a.g1 + kXcds - 1) / kXcds;
   const int nk = c8 * kXcds;
   const int per = (nk + kScanTPB - 1) / kScanTPB;
@@ -220,24 +299,6 @@ __device__ void scan2_part(const WinArgs& a, int p, uint32_t* scratch) {
     const uint32_t c = a.H[(size_t)p * a.g1 + w];
     a.Off[(size_t)p * a.g1 + w] = run;
     run += c;
-  }
-  for (uint32_t j = threadIdx.x; j < kp; j += kScanTPB) {
-    Item it;
-    it.p = p;
-    it.lo = start + (uint32_t)(j * a.rs);
-    it.hi = (uint32_t)min((int64_t)start + rp, (int64_t)it.lo + a.rs);
-    it.first = ibase;
-    it.kp = kp;
-    it.reserved[0] = it.reserved[1] = it.reserved[2] = 0;
-    a.items[ibase + j] = it;
-  }
-  if (threadIdx.x == 0) {
-    a.pinfo[p].first = ibase;
-    a.pinfo[p].kp = kp;
-    a.pinfo[p].start = start;
-    a.pinfo[p].reserved = 0;
-    a.pfill[p] = 0;
-    if (p == a.nparts - 1) a.hdr[1] = ibase + kp;
   }
   __syncthreads();
 }
@@ -1046,6 +1107,19 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scan1(const char* desc, MultiL
   }
 }
 
+__global__ __launch_bounds__(kScanTPB) void k_wam_scanp(const char* desc, MultiLim lim) {
+  __shared__ uint32_t r[kMaxParts], st[kMaxParts], kc[kMaxParts], base[kMaxParts];
+  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  __shared__ WinArgs sa;
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  uint32_t cur = ~0u;
+  for (uint32_t b = blockIdx.x; b < v.hdr->nb; b += gridDim.x) {
+    load_args(v, b, &sa, &cur);
+    plan_items(sa, r, st, kc, base, scratch);
+  }
+}
+
 __global__ __launch_bounds__(kScanTPB) void k_wam_scan2(const char* desc, MultiLim lim) {
   __shared__ uint32_t scratch[kScanTPB / 64 + 1];
   __shared__ WinArgs sa;
@@ -1149,7 +1223,7 @@ Plan make_plan(int64_t n, int nval, int nacc) {
   else p.chunk = std::min<int64_t>(65536, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
   p.g1 = (int)((n + p.chunk - 1) / p.chunk);
   const int64_t part_rows = g_tuning.part_rows > 0 ? g_tuning.part_rows : 16384;
-  p.nparts = (int)std::min<int64_t>(4096, std::max<int64_t>(8, next_pow2((n + part_rows - 1) / part_rows)));
+  p.nparts = (int)std::min<int64_t>(kMaxParts, std::max<int64_t>(8, next_pow2((n + part_rows - 1) / part_rows)));
   p.pbits = ilog2(p.nparts);
   p.rs = g_tuning.piece_rows > 0 ? g_tuning.piece_rows : 8192;
   p.max_items = p.nparts + (int)((n + p.rs - 1) / p.rs);
@@ -1396,6 +1470,7 @@ int launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
   LMS_LAUNCH("k_wam_init", k_wam_init, dim3(4), dim3(256), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_hist", k_wam_hist, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
   LMS_LAUNCH("k_wam_scan1", k_wam_scan1, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
+  LMS_LAUNCH("k_wam_scanp", k_wam_scanp, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scan2", k_wam_scan2, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
   LMS_LAUNCH("k_wam_agg", k_wam_agg<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
@@ -1420,6 +1495,7 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
     const size_t plds = (size_t)p.nparts * 4;
     LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(p.g1), dim3(kScanTPB), plds, st, a);
     LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
+    LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kScanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
     // loops over aggregates are unrolled to the smallest bound covering nagg
     if (nagg <= 2) launch_tail<2>(p, a, plds, st);
@@ -1550,7 +1626,7 @@ extern "C" int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nb
 
 extern "C" int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lms_stream stream) {
   if (!cfg || !workspace || cfg->nbatch <= 0) return set_error(LMS_EINVAL, "bad multi-batch launch arguments");
-  if (cfg->grid_scan <= 0 || cfg->grid_agg <= 0 || cfg->max_nparts <= 0 || cfg->max_nparts > 4096 ||
+  if (cfg->grid_scan <= 0 || cfg->grid_agg <= 0 || cfg->max_nparts <= 0 || cfg->max_nparts > kMaxParts ||
       cfg->agg_lds > (uint64_t)(kLdsLimit - kArgsLds) ||
       !(cfg->ma == 2 || cfg->ma == 4 || cfg->ma == 6 || cfg->ma == 8))
     return set_error(LMS_EINVAL, "bad multi-batch configuration");

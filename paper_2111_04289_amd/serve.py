@@ -180,6 +180,7 @@ class Query:
                 self.ctl = lms.Admission(deadline_ms=eng.bound_ms, poll_ms=eng.poll_ms)
         self.state = None
         self.drained = False
+        self.closed = False  # the end-of-stream batch has taken the controller's buffer
         if name == "slide":
             self.state = lms.WindowState(lms.Window(0, 10000, 1000, 0), SLIDE_AGGS, eng.max_keys, 64, eng.dev,
                                          self.stream)
@@ -376,7 +377,7 @@ class Engine:
             if self.mode == "served" and now >= next_poll:
                 next_poll = now + self.poll_ms
                 for q in self.queries.values():
-                    if len(q.inflight) + len(q.waiting) >= self.slots:
+                    if q.closed or len(q.inflight) + len(q.waiting) >= self.slots:
                         continue
                     new = arr[q.next_ds:arrived]
                     d = q.ctl.poll(now, new, np.full(len(new), DS_ROWS, np.int64))
@@ -421,10 +422,12 @@ class Engine:
                     if q.next_batch_ds < nds:
                         busy = True
                         if self.mode == "served" and not q.inflight and not q.waiting:
-                            # deliver the rest regardless of the deadline
+                            # deliver the rest regardless of the deadline; the
+                            # controller's buffer is handed over with it
                             d0, d1 = q.next_batch_ds, nds
                             q.next_batch_ds = d1
                             q.next_ds = nds
+                            q.closed = True
                             b = Batch(q.name, d0, d1, (d1 - d0) * DS_ROWS, now, float(arr[d0]))
                             b.need = q.need(b.rows)
                             q.waiting.append(b)

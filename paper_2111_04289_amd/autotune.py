@@ -30,14 +30,15 @@ PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json"
 
 SPACE = {
     "chunk_rows": [0, 2048, 8192, 32768, 65536],
-    "part_rows": [0, 4096, 8192, 32768],
-    "piece_rows": [0, 4096, 16384],
-    "grid_per_cu": [0, 2, 8],
     "lds_groups": [0, 1024, 512],
+    "part_rows": [0, 4096, 8192, 32768],
+    "piece_rows": [0, 2048, 4096, 16384],
+    "grid_per_cu": [0, 2, 8],
 }
-# Coordinates of the descent; partition size and LDS table size move together
-# (a smaller table only pays off with smaller partitions).
-COORDS = [("chunk_rows",), ("part_rows", "lds_groups"), ("piece_rows",), ("grid_per_cu",)]
+# Coordinates of the descent.  Partition and piece sizes default to multiples of
+# the LDS table size, so the table-size coordinate moves all three coherently;
+# the others then refine.
+COORDS = [("lds_groups",), ("chunk_rows",), ("part_rows",), ("piece_rows",), ("grid_per_cu",)]
 DEFAULT = {k: 0 for k in SPACE}
 
 

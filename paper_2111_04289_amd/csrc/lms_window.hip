@@ -34,6 +34,11 @@ namespace {
 
 constexpr int kScanTPB = 256;
 constexpr int kAggTPB = 512;
+// Waves per SIMD the aggregation kernels are compiled for: 4 (<= 128 VGPRs)
+// lets two 512-thread workgroups share a CU when their LDS tables fit
+// (lds_groups 1024); with more than 4 accumulators that would spill, so those
+// instances keep the register budget of 2.
+constexpr int agg_waves(int ma) { return ma <= 4 ? 4 : 2; }
 constexpr uint64_t kEmptyKey = 0x8000000000000000ull;
 constexpr uint64_t kEmptyGid = ~0ull;
 constexpr int kLdsLimit = 160 * 1024;
@@ -654,17 +659,14 @@ __device__ void emit_tumbling(const WinArgs& a, Lds& s, int64_t b0) {
         const uint32_t cnt = s.gcnt[g];
         a.okey[idx] = key_of(a, s, (uint32_t)(gid >> 32));
         a.ows[idx] = a.origin + (b0 + (int64_t)(uint32_t)gid) * a.len;
-#pragma unroll
-        for (int k = 0; k < MA; ++k) {
-          if (k < a.nagg) {
-            const int fn = a.afn[k];
-            if (fn == LMS_COUNT) {
-              ((int64_t*)a.oagg[k])[idx] = cnt;
-            } else {
-              const uint64_t v = s.acc[(size_t)a.aacc[k] * a.eg + g];
-              if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)v) / (double)cnt;
-              else ((int64_t*)a.oagg[k])[idx] = (int64_t)v;
-            }
+        for (int k = 0; k < a.nagg; ++k) {
+          const int fn = a.afn[k];
+          if (fn == LMS_COUNT) {
+            ((int64_t*)a.oagg[k])[idx] = cnt;
+          } else {
+            const uint64_t v = s.acc[(size_t)a.aacc[k] * a.eg + g];
+            if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)v) / (double)cnt;
+            else ((int64_t*)a.oagg[k])[idx] = (int64_t)v;
           }
         }
       }
@@ -780,20 +782,17 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
     }
     a.okey[idx] = key_of(a, s, kid);
     a.ows[idx] = a.origin + ((int64_t)w + wbase) * a.slide;
+    for (int k = 0; k < a.nagg; ++k) {
+      const int fn = a.afn[k];
+      if (fn == LMS_COUNT) {
+        ((int64_t*)a.oagg[k])[idx] = cnt;
+      } else {
+        const int slot = a.aacc[k];
+        uint64_t x = acc[0];
 #pragma unroll
-    for (int k = 0; k < MA; ++k) {
-      if (k < a.nagg) {
-        const int fn = a.afn[k];
-        if (fn == LMS_COUNT) {
-          ((int64_t*)a.oagg[k])[idx] = cnt;
-        } else {
-          const int slot = a.aacc[k];
-          uint64_t x = acc[0];
-#pragma unroll
-          for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
-          if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)x) / (double)cnt;
-          else ((int64_t*)a.oagg[k])[idx] = (int64_t)x;
-        }
+        for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
+        if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)x) / (double)cnt;
+        else ((int64_t*)a.oagg[k])[idx] = (int64_t)x;
       }
     }
   }
@@ -983,13 +982,13 @@ __device__ void merge_part(const WinArgs& a, uint32_t p, char* lds_raw) {
 }
 
 template <int MA>
-__global__ __launch_bounds__(kAggTPB) void k_wa_agg(WinArgs a) {
+__global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wa_agg(WinArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   agg_item<MA>(a, blockIdx.x, lds_raw);
 }
 
 template <int MA>
-__global__ __launch_bounds__(kAggTPB) void k_wa_merge(WinArgs a) {
+__global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wa_merge(WinArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   merge_part<MA>(a, blockIdx.x, lds_raw);
 }
@@ -1011,11 +1010,11 @@ struct MultiHdr {
   uint32_t nitems;      // total aggregation item slots (per batch: its bound)
   uint32_t max_nparts;  // largest partition count of a batch
   uint32_t agg_lds;     // largest aggregation LDS plan of a batch
-  uint32_t max_nagg;    // largest aggregate count of a batch
+  uint32_t max_nacc;    // largest accumulator count of a batch
   uint32_t reserved[9];
 };
 
-// Limits a launch was configured for (LDS it was given, unroll bound).
+// Limits a launch was configured for (LDS it was given, accumulator unroll bound).
 struct MultiLim {
   uint32_t parts, agg_lds, ma, pad;
 };
@@ -1023,7 +1022,7 @@ struct MultiLim {
 // A job whose descriptors exceed what the launch was configured for (a graph
 // replayed after a larger job was prepared) is rejected as a whole.
 __device__ __forceinline__ bool multi_fits(const MultiHdr* h, MultiLim l) {
-  return h->max_nparts <= l.parts && h->agg_lds <= l.agg_lds && h->max_nagg <= l.ma;
+  return h->max_nparts <= l.parts && h->agg_lds <= l.agg_lds && h->max_nacc <= l.ma;
 }
 
 struct MultiView {
@@ -1148,7 +1147,7 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scatter(const char* desc, Mult
 }
 
 template <int MA>
-__global__ __launch_bounds__(kAggTPB) void k_wam_agg(const char* desc, MultiLim lim) {
+__global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wam_agg(const char* desc, MultiLim lim) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ WinArgs sa;
   const MultiView v = multi_view(desc);
@@ -1164,7 +1163,7 @@ __global__ __launch_bounds__(kAggTPB) void k_wam_agg(const char* desc, MultiLim 
 }
 
 template <int MA>
-__global__ __launch_bounds__(kAggTPB) void k_wam_merge(const char* desc, MultiLim lim) {
+__global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wam_merge(const char* desc, MultiLim lim) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ WinArgs sa;
   const MultiView v = multi_view(desc);
@@ -1216,19 +1215,24 @@ int64_t gcd64(int64_t x, int64_t y) {
 
 lms_tuning g_tuning{0, 0, 0, 0, 0, 0};
 
+// Unroll bound of the per-accumulator loops (the kernels are instantiated for 2, 4, 6, 8).
+int acc_bound(int nacc) { return nacc <= 2 ? 2 : nacc <= 4 ? 4 : nacc <= 6 ? 6 : 8; }
+
 Plan make_plan(int64_t n, int nval, int nacc) {
   Plan p{};
   p.n = n;
   if (g_tuning.chunk_rows > 0) p.chunk = next_pow2(g_tuning.chunk_rows);
   else p.chunk = std::min<int64_t>(65536, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
   p.g1 = (int)((n + p.chunk - 1) / p.chunk);
-  const int64_t part_rows = g_tuning.part_rows > 0 ? g_tuning.part_rows : 16384;
-  p.nparts = (int)std::min<int64_t>(kMaxParts, std::max<int64_t>(8, next_pow2((n + part_rows - 1) / part_rows)));
-  p.pbits = ilog2(p.nparts);
-  p.rs = g_tuning.piece_rows > 0 ? g_tuning.piece_rows : 8192;
-  p.max_items = p.nparts + (int)((n + p.rs - 1) / p.rs);
+  // the LDS group table sets the scale: by default a partition targets 8 rows
+  // per table slot and an aggregation piece 4 (16384 and 8192 at 2048 slots)
   p.eg = g_tuning.lds_groups > 0 ? g_tuning.lds_groups : 2048;
   p.ek = p.eg / 2;
+  const int64_t part_rows = g_tuning.part_rows > 0 ? g_tuning.part_rows : 8 * (int64_t)p.eg;
+  p.nparts = (int)std::min<int64_t>(kMaxParts, std::max<int64_t>(8, next_pow2((n + part_rows - 1) / part_rows)));
+  p.pbits = ilog2(p.nparts);
+  p.rs = g_tuning.piece_rows > 0 ? g_tuning.piece_rows : 4 * (int64_t)p.eg;
+  p.max_items = p.nparts + (int)((n + p.rs - 1) / p.rs);
   while (lds_bytes(p.ek, p.eg, nacc) + kArgsLds > (size_t)kLdsLimit && p.eg > 1024) {
     p.eg /= 2;
     p.ek /= 2;
@@ -1497,10 +1501,11 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
     LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kScanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
-    // loops over aggregates are unrolled to the smallest bound covering nagg
-    if (nagg <= 2) launch_tail<2>(p, a, plds, st);
-    else if (nagg <= 4) launch_tail<4>(p, a, plds, st);
-    else if (nagg <= 6) launch_tail<6>(p, a, plds, st);
+    // loops over accumulators are unrolled to the smallest bound covering them
+    const int ma = acc_bound(a.nacc);
+    if (ma == 2) launch_tail<2>(p, a, plds, st);
+    else if (ma == 4) launch_tail<4>(p, a, plds, st);
+    else if (ma == 6) launch_tail<6>(p, a, plds, st);
     else launch_tail<8>(p, a, plds, st);
   }
   return check_hip(hipGetLastError(), "window_agg launch");
@@ -1578,7 +1583,7 @@ extern "C" int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nb
   o += align_up((size_t)(nbatch + 1) * 4, 16);
   WinArgs* args = (WinArgs*)(hbuf + align_up(o, 16));
   size_t off = dbytes;
-  int max_nparts = 1;
+  int max_nparts = 1, max_nacc = 0;
   uint64_t c = 0, pp = 0, it = 0;
   size_t agg_lds = 0;
   for (int b = 0; b < nbatch; ++b) {
@@ -1595,6 +1600,7 @@ extern "C" int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nb
     pp += (uint64_t)p.nparts;
     it += (uint64_t)p.max_items;
     max_nparts = std::max(max_nparts, p.nparts);
+    max_nacc = std::max(max_nacc, args[b].nacc);
     agg_lds = std::max(agg_lds, p.lds);
   }
   if (c >= (1ull << 32) || pp >= (1ull << 32) || it >= (1ull << 32)) return set_error(LMS_EINVAL, "job too large");
@@ -1606,9 +1612,9 @@ extern "C" int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nb
   hdr->nitems = (uint32_t)it;
   hdr->max_nparts = (uint32_t)max_nparts;
   hdr->agg_lds = (uint32_t)agg_lds;
-  hdr->max_nagg = (uint32_t)std::max(nagg, 0);
+  hdr->max_nacc = (uint32_t)max_nacc;
   cfg->nbatch = nbatch;
-  cfg->ma = nagg <= 2 ? 2 : nagg <= 4 ? 4 : nagg <= 6 ? 6 : 8;
+  cfg->ma = acc_bound(max_nacc);
   cfg->max_nparts = max_nparts;
   const int per_cu = g_tuning.grid_per_cu > 0 ? g_tuning.grid_per_cu : 4;
   cfg->grid_scan = num_cus() * per_cu;

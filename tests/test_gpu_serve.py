@@ -106,11 +106,13 @@ def test_plain_trigger_form_and_cpu_placement(serve, stream):
 def test_admission_waits_for_hbm(serve, stream):
     data, cols = stream
     from paper_2111_04289_amd import serve as s
-    # a budget that holds one sliding batch (its inputs and emitted windows) but
-    # not a filter batch beside it forces batches to queue for memory
-    budget = (1 << 20) * s.MAX_EMIT_WINDOWS * 56 + 1600000 * 24 + (16 << 20)
-    eng, res = run(serve, data, "served", ("slide", "fp"), hbm_budget=budget, slots=3)
+    # a budget that holds any one sliding batch (its inputs and the emitted
+    # windows it reserves) but never a tumbling batch beside it: both controllers
+    # admit their first batch at the same poll, so one of them must wait
+    budget = (1 << 20) * s.MAX_EMIT_WINDOWS * 56 + len(cols[0]) * 24 + (1 << 20)
+    eng, res = run(serve, data, "served", ("slide", "tumble"), hbm_budget=budget, slots=3)
     assert res["hbm_waits"] > 0
     slide_exp = oracle.window_agg(cols, 1, 0, 10000, 1000, 0, s.SLIDE_AGGS, [(2, oracle.LT, 314573)])
     assert_window_equal(windows(eng, "slide"), slide_exp, s.SLIDE_AGGS, "slide under an HBM budget")
-    check_fp(eng, cols)
+    tumble_exp = oracle.window_agg(cols, 1, 0, 1000, 0, 0, s.TUMBLE_AGGS)
+    assert_window_equal(windows(eng, "tumble"), tumble_exp, s.TUMBLE_AGGS, "tumble under an HBM budget")

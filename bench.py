@@ -51,6 +51,29 @@ def parse():
     return ap.parse_args()
 
 
+def traffic_record(kernels_prefix="k_wa_"):
+    """HBM bytes per launch of the window-agg kernel sequence from the committed
+    rocprofv3 counter summary, or None when the summary is missing or was taken
+    on other kernel sources than the ones built now."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "window_agg_16M_sliding_traffic.txt")
+    src = os.path.join(here, "paper_2111_04289_amd", "csrc", "lms_window.hip")
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    try:
+        return {"fetch_bytes": float(kv["fetch_bytes_per_launch"]), "write_bytes": float(kv["write_bytes_per_launch"])}
+    except (KeyError, ValueError):
+        return None
+
+
 def run_serving(args, log):
     """The served form (admission per query, continuous batching, learned
     placement when a trained model is packaged) against the plain fixed-trigger
@@ -245,6 +268,7 @@ def main():
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step / 1e3) / 1e6
 
+    traffic = traffic_record()
     groups_n = counts["groups"]
     # algorithmic bytes of the windowed group-by: referenced columns read once
     # (ts 8 + key 8 + val 4 + f 4) and the result written once (7 x 8 bytes)
@@ -307,7 +331,10 @@ def main():
         "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
         "roofline": {"kernel": "window_agg (k_wa_* launch sequence)", "bound": "hbm",
                      "achieved": round(achieved, 1) if achieved else None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None, "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                     "traffic": (round(traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None),
+                     "traffic_fetch_write": ([round(traffic["fetch_bytes"]), round(traffic["write_bytes"])]
+                                             if traffic else None),
                      "alg_bytes_per_launch": wa_bytes, "ms_per_launch": round(wa_ms, 4)},
         "cpu_baseline": cpu,
         "ops": ops,

@@ -81,9 +81,13 @@ struct WinArgs {
   PartInfo* pinfo;
   Item* items;
   uint32_t* pfill;  // nparts: partial records reserved so far in each split partition
-  int64_t* skey;
-  uint32_t* spane;
-  void* sval[kMaxAggs];
+  // staged rows, one record of `rec` bytes per passing row: key (8 B) at 0,
+  // 8-byte values, pane (4 B) at pane_off, 4-byte values, padding to 8 B --
+  // one contiguous record keeps a partition's short per-chunk segment to one
+  // or two cache lines instead of a partial line in each of several arrays
+  char* srec;
+  int32_t rec, pane_off;
+  int32_t voff[kMaxAggs];  // byte offset of staged value column v in a record
   int64_t* pkey;
   uint32_t* ppane;
   uint32_t* pcnt;
@@ -195,15 +199,17 @@ constexpr int kMaxParts = 4096;  // partitions of one batch (make_plan's bound)
 // workgroup; r, st, kc, base are kMaxParts-word LDS arrays):
 //  * a partition of more than rs rows gives ceil(R / rs) pieces, whose partial
 //    records k_wa_merge combines;
-//  * a partition of (rs/2, rs] rows is one item;
-//  * non-empty partitions of at most rs/2 rows are packed: consecutive ones
-//    whose starts fall in the same rs/2-row bucket form one item of at most
-//    rs rows (a larger partition between two of them always starts a new
-//    bucket), so low selectivity or small batches give few, fuller items.
+//  * a partition of (eg/4, rs] rows is one item;
+//  * non-empty partitions of at most eg/4 rows are packed: consecutive ones
+//    whose starts fall in the same eg/4-row bucket form one item of at most
+//    eg/2 rows -- few enough groups for the LDS table even when every row is a
+//    group of its own -- and a larger partition between two of them always
+//    starts a new bucket.  Low selectivity or small batches then give few,
+//    fuller items instead of thousands of nearly empty ones.
 __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t* kc, uint32_t* base,
                            uint32_t* scratch) {
   const int np = a.nparts;
-  const uint32_t rs = (uint32_t)a.rs, half = rs / 2;
+  const uint32_t rs = (uint32_t)a.rs, pack = (uint32_t)a.eg / 4;
   for (int p = threadIdx.x; p < np; p += kScanTPB) {
     const uint32_t v = a.Rp[p];
     r[p] = v;
@@ -216,15 +222,15 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
     uint32_t k = 0;
     if (v > rs) {
       k = (v + rs - 1) / rs;
-    } else if (v > half) {
+    } else if (v > pack) {
       k = 1;
     } else if (v > 0) {  // packed: the first of its bucket leads the item
-      const uint32_t b = st[p] / half;
+      const uint32_t b = st[p] / pack;
       bool leader = true;
       for (int q = p - 1; q >= 0; --q) {
         const uint32_t w = r[q];
         if (w == 0) continue;
-        leader = w > half || st[q] / half != b;
+        leader = w > pack || st[q] / pack != b;
         break;
       }
       k = leader ? 1 : 0;
@@ -250,10 +256,10 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
         }
       } else {
         uint32_t hi = s0 + v;
-        if (v <= half) {  // extend over the rest of the bucket
-          const uint32_t b = s0 / half;
+        if (v <= pack) {  // extend over the rest of the bucket
+          const uint32_t b = s0 / pack;
           int q = p + 1;
-          while (q < np && (r[q] == 0 || (r[q] <= half && st[q] / half == b))) ++q;
+          while (q < np && (r[q] == 0 || (r[q] <= pack && st[q] / pack == b))) ++q;
           hi = q < np ? st[q] : total;
         }
         it.kp = 1;
@@ -365,13 +371,14 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
         range_err = true;
         qp = 0;
       }
-      a.skey[pos] = key[u];
-      a.spane[pos] = (uint32_t)qp;
+      char* const r = a.srec + (size_t)pos * a.rec;
+      *(int64_t*)r = key[u];
+      *(uint32_t*)(r + a.pane_off) = (uint32_t)qp;
 #pragma unroll
       for (int v = 0; v < MA; ++v) {
         if (v < a.nval) {
-          if (a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_F32) ((uint32_t*)a.sval[v])[pos] = (uint32_t)val[u][v];
-          else ((uint64_t*)a.sval[v])[pos] = val[u][v];
+          if (a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_F32) *(uint32_t*)(r + a.voff[v]) = (uint32_t)val[u][v];
+          else *(uint64_t*)(r + a.voff[v]) = val[u][v];
         }
       }
     }
@@ -509,20 +516,21 @@ struct Elem {
 
 template <int MA>
 __device__ __forceinline__ void load_row(const WinArgs& a, uint32_t e, Elem<MA>& x) {
-  x.key = a.skey[e];
-  x.pane = a.spane[e];
+  const char* const r = a.srec + (size_t)e * a.rec;
+  x.key = *(const int64_t*)r;
+  x.pane = *(const uint32_t*)(r + a.pane_off);
   x.cnt = 1;
   uint64_t raw[MA];  // staged value v: int64, or double bits for float columns
 #pragma unroll
   for (int v = 0; v < MA; ++v) {
     raw[v] = 0;
     if (v < a.nval) {
-      const void* c = a.sval[v];
+      const char* c = r + a.voff[v];
       switch (a.vdt[v]) {
-        case LMS_I32: raw[v] = (uint64_t)(int64_t)((const int32_t*)c)[e]; break;
-        case LMS_I64: raw[v] = ((const uint64_t*)c)[e]; break;
-        case LMS_F32: raw[v] = (uint64_t)__double_as_longlong((double)((const float*)c)[e]); break;
-        default: raw[v] = ((const uint64_t*)c)[e]; break;
+        case LMS_I32: raw[v] = (uint64_t)(int64_t)*(const int32_t*)c; break;
+        case LMS_I64: raw[v] = *(const uint64_t*)c; break;
+        case LMS_F32: raw[v] = (uint64_t)__double_as_longlong((double)*(const float*)c); break;
+        default: raw[v] = *(const uint64_t*)c; break;
       }
     }
   }
@@ -1215,6 +1223,9 @@ int64_t gcd64(int64_t x, int64_t y) {
 
 lms_tuning g_tuning{0, 0, 0, 0, 0, 0};
 
+// Bytes of a staged record for nval value columns, whatever their widths.
+size_t rec_bound(int nval) { return align_up(8 + 4 + 8 * (size_t)nval, 8); }
+
 // Unroll bound of the per-accumulator loops (the kernels are instantiated for 2, 4, 6, 8).
 int acc_bound(int nacc) { return nacc <= 2 ? 2 : nacc <= 4 ? 4 : nacc <= 6 ? 6 : 8; }
 
@@ -1253,10 +1264,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   PartInfo* pinfo = c.take<PartInfo>(p.nparts);
   Item* items = c.take<Item>(p.max_items);
   uint32_t* pfill = c.take<uint32_t>(p.nparts);
-  int64_t* skey = c.take<int64_t>(p.n);
-  uint32_t* spane = c.take<uint32_t>(p.n);
-  void* sval[kMaxAggs] = {};
-  for (int v = 0; v < p.nval; ++v) sval[v] = c.take<uint64_t>(p.n);
+  char* srec = c.take<char>((size_t)p.n * rec_bound(p.nval));
   int64_t* pkey = c.take<int64_t>(p.n);
   uint32_t* ppane = c.take<uint32_t>(p.n);
   uint32_t* pcnt = c.take<uint32_t>(p.n);
@@ -1270,9 +1278,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
     a->pinfo = pinfo;
     a->items = items;
     a->pfill = pfill;
-    a->skey = skey;
-    a->spane = spane;
-    for (int v = 0; v < kMaxAggs; ++v) a->sval[v] = sval[v];
+    a->srec = srec;
     a->pkey = pkey;
     a->ppane = ppane;
     a->pcnt = pcnt;
@@ -1314,6 +1320,21 @@ int resolve_aggs(const lms_batch* in, const lms_proj* projs, int32_t nproj, cons
     a->accval[s] = v;
     a->aacc[k] = s;
   }
+  // staged record: key, 8-byte values, pane, 4-byte values, padded to 8 bytes
+  int off = 8;
+  for (int v = 0; v < a->nval; ++v)
+    if (a->vdt[v] == LMS_I64 || a->vdt[v] == LMS_F64) {
+      a->voff[v] = off;
+      off += 8;
+    }
+  a->pane_off = off;
+  off += 4;
+  for (int v = 0; v < a->nval; ++v)
+    if (a->vdt[v] == LMS_I32 || a->vdt[v] == LMS_F32) {
+      a->voff[v] = off;
+      off += 4;
+    }
+  a->rec = (int32_t)align_up((size_t)off, 8);
   return LMS_OK;
 }
 

@@ -357,16 +357,21 @@ class Engine:
             q.results.append((b.d0, b.d1, [t.numpy() if hasattr(t, "numpy") else t for t in b.result]))
 
     # ---- main loop --------------------------------------------------------------------
-    def run(self, drain_s=30.0):
+    def run(self, drain_s=30.0, report_every_ms=10000.0):
         arr = self.data.arr
         nds = len(arr)
         end_ms = float(arr[-1]) if nds else 0.0
+        next_report = report_every_ms
         next_poll = 0.0
         next_trigger = self.trigger_ms
         last_admit = {q: 0.0 for q in self.queries}
         while True:
             now = self.now()
             arrived = int(np.searchsorted(arr, now, side="right"))
+            if now >= next_report:
+                next_report += report_every_ms
+                done = {q.name: (len(q.batch_rows), q.rows_done) for q in self.queries.values()}
+                self.log(f"{self.mode} t={now / 1e3:.0f} s: {arrived} datasets arrived; (batches, rows) done {done}")
             # completions
             for q in self.queries.values():
                 for b in list(q.inflight):

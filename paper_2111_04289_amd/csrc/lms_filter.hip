@@ -2,9 +2,10 @@
 // stream compaction of the rows that pass a conjunction of predicates.
 //
 // Three launches: per-tile counts of passing rows, one scan of the tile
-// counts, then a write pass that ranks each round of rows with a block prefix
-// and stages them in LDS, so rows keep their input order without any global
-// atomic and the output writes are coalesced.
+// counts, then a write pass that ranks each round of rows with wave ballots
+// and a block prefix, so rows keep their input order without any global
+// atomic, and both the column loads and the output writes are contiguous per
+// wave.
 #include <algorithm>
 
 #include "lms_internal.h"
@@ -29,20 +30,20 @@ struct FpArgs {
   int64_t* d_count;
 };
 
-// Each thread owns kRows consecutive rows of a round of kTPB * kRows rows, so
-// its predicate loads are contiguous and a block prefix over per-thread counts
-// ranks the passing rows in input order.
+// A round is kRows sub-rounds of kTPB consecutive rows; in sub-round u lane t
+// takes row b0 + u * kTPB + t, so every column load of a wave is one
+// contiguous run.
 __global__ __launch_bounds__(kTPB) void k_fp_count(FpArgs a) {
   __shared__ uint32_t scratch[kTPB / 64 + 1];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   uint32_t c = 0;
-  for (int64_t b = lo + (int64_t)threadIdx.x * kRows; b < hi; b += (int64_t)kTPB * kRows) {
+  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kRows) {
     int64_t idx[kRows];
     bool ok[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) {
-      idx[u] = b + u;
+      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
       ok[u] = idx[u] < hi;
     }
     rows_pass<kRows>(a.q, idx, ok);
@@ -79,41 +80,56 @@ __device__ __forceinline__ void put_bits(void* col, int dt, int64_t r, uint64_t 
   else ((uint64_t*)col)[r] = v;
 }
 
-// Stable compaction: the passing rows of a round are ranked, staged column by
-// column in LDS at their rank, and copied out with consecutive threads writing
-// consecutive output rows.
+// Stable compaction.  Ranks come from wave ballots: a passing row's rank is
+// the passing rows of earlier (sub-round, wave) pairs -- sub-round major, as
+// rows are ordered -- plus those of lower lanes in its wave's ballot.  The
+// passing lanes of a wave therefore write one contiguous run of each output
+// column, and every load is contiguous too; no value is staged.
 __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
-  __shared__ uint32_t scratch[kTPB / 64 + 1];
-  __shared__ uint64_t stage[kTPB * kRows];
+  constexpr int kWaves = kTPB / 64;
+  __shared__ uint32_t wpre[kRows * kWaves + 1];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   const int ncol = a.nkeep + a.q.nproj;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1;
   int64_t run = a.tile_off[blockIdx.x];
   for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kRows) {
-    const int64_t b = b0 + (int64_t)threadIdx.x * kRows;
-    bool pass[kRows];
     int64_t idx[kRows];
-    uint32_t c = 0;
+    bool pass[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) {
-      idx[u] = b + u;
+      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
       pass[u] = idx[u] < hi;
     }
     rows_pass<kRows>(a.q, idx, pass);
+    uint64_t m[kRows];
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) c += pass[u];
-    uint32_t tot;
-    const uint32_t r0 = block_excl_scan<kTPB>(c, scratch, &tot);
+    for (int u = 0; u < kRows; ++u) {
+      m[u] = __ballot(pass[u]);
+      if (lane == 0) wpre[u * kWaves + wave] = (uint32_t)__popcll(m[u]);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int i = 0; i < kRows * kWaves; ++i) {
+        const uint32_t v = wpre[i];
+        wpre[i] = t;
+        t += v;
+      }
+      wpre[kRows * kWaves] = t;
+    }
+    __syncthreads();
+    int64_t r[kRows];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) r[u] = run + wpre[u * kWaves + wave] + __popcll(m[u] & below);
     for (int j = 0; j < ncol; ++j) {
-      uint32_t r = r0;
 #pragma unroll
       for (int u = 0; u < kRows; ++u)
-        if (pass[u]) stage[r++] = out_bits(a, j, b + u);
-      __syncthreads();
-      for (uint32_t t = threadIdx.x; t < tot; t += kTPB) put_bits(a.out[j], a.odt[j], run + t, stage[t]);
-      __syncthreads();
+        if (pass[u]) put_bits(a.out[j], a.odt[j], r[u], out_bits(a, j, idx[u]));
     }
-    run += tot;
+    run += wpre[kRows * kWaves];
+    __syncthreads();  // wpre is rewritten by the next round
   }
 }
 

@@ -140,21 +140,24 @@ __device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)
 
 // Probe pass: walks every row's chain once and records, per row, its match
 // count and first payload (packed count << 32 | payload) for the write pass,
-// plus the tile's total.
+// plus the tile's total.  A round is kProbe sub-rounds of kTPB consecutive
+// rows; lane t takes row b0 + u * kTPB + t of sub-round u, so key loads and
+// record stores are contiguous per wave.
 __global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
   __shared__ uint32_t scratch[kTPB / 64 + 1];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
   uint32_t c = 0;
-  for (int64_t b = lo + (int64_t)threadIdx.x * kProbe; b < hi; b += (int64_t)kTPB * kProbe) {
-    int64_t k[kProbe];
+  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kProbe) {
+    int64_t k[kProbe], idx[kProbe];
     bool valid[kProbe];
     uint32_t cnt[kProbe];
     uint32_t first[kProbe];
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
-      valid[u] = b + u < hi;
-      k[u] = valid[u] ? load_i64(a.pkey, a.kdt, b + u) : 0;
+      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
+      valid[u] = idx[u] < hi;
+      k[u] = valid[u] ? load_i64(a.pkey, a.kdt, idx[u]) : 0;
       cnt[u] = 0;
       first[u] = 0;
     }
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
     });
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
-      if (valid[u]) a.hits[b + u] = ((uint64_t)cnt[u] << 32) | first[u];
+      if (valid[u]) a.hits[idx[u]] = ((uint64_t)cnt[u] << 32) | first[u];
       c += cnt[u];
     }
   }
@@ -183,35 +186,58 @@ __global__ __launch_bounds__(kScanThreads) void k_jp_scan(ProbeArgs a) {
 }
 
 // Write pass: reads the recorded hits (no table access for rows with at most
-// one match), ranks each round of rows with a block prefix from the tile's
-// offset, and writes the pairs grouped by ascending probe row; a row with
-// several matches walks its chain again, in the same order.
+// one match) in the probe pass's row layout and ranks the pairs in row order:
+// a wave scan of the match counts plus a block prefix over (sub-round, wave)
+// totals, sub-round major.  The pairs come out grouped by ascending probe row;
+// a row with several matches walks its chain again, in the same order.
 __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
-  __shared__ uint32_t scratch[kTPB / 64 + 1];
+  constexpr int kWaves = kTPB / 64;
+  __shared__ uint32_t wpre[kProbe * kWaves + 1];
   const int64_t lo = (int64_t)blockIdx.x * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t run = a.tile_off[blockIdx.x];
   for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kProbe) {
-    const int64_t b = b0 + (int64_t)threadIdx.x * kProbe;
+    int64_t idx[kProbe];
     uint64_t h[kProbe];
+    uint32_t ex[kProbe];
 #pragma unroll
-    for (int u = 0; u < kProbe; ++u) h[u] = b + u < hi ? a.hits[b + u] : 0;
-    uint32_t c = 0;
+    for (int u = 0; u < kProbe; ++u) {
+      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
+      h[u] = idx[u] < hi ? a.hits[idx[u]] : 0;
+      const uint32_t v = (uint32_t)(h[u] >> 32);
+      uint32_t x = v;
 #pragma unroll
-    for (int u = 0; u < kProbe; ++u) c += (uint32_t)(h[u] >> 32);
-    uint32_t tot;
-    int64_t o = run + block_excl_scan<kTPB>(c, scratch, &tot);
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+      }
+      ex[u] = x - v;
+      if (lane == 63) wpre[u * kWaves + wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t t = 0;
+      for (int i = 0; i < kProbe * kWaves; ++i) {
+        const uint32_t v = wpre[i];
+        wpre[i] = t;
+        t += v;
+      }
+      wpre[kProbe * kWaves] = t;
+    }
+    __syncthreads();
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
       const uint32_t cu = (uint32_t)(h[u] >> 32);
       if (cu == 0) continue;
+      const int64_t o = run + wpre[u * kWaves + wave] + ex[u];
       if (cu == 1) {
         if (o < a.cap) {
-          a.out_idx[o] = (uint32_t)(b + u);
+          a.out_idx[o] = (uint32_t)idx[u];
           a.out_pay[o] = (int32_t)(uint32_t)h[u];
         }
       } else {
-        const int64_t k = load_i64(a.pkey, a.kdt, b + u);
+        const int64_t k = load_i64(a.pkey, a.kdt, idx[u]);
         int64_t r = o;
         uint64_t s = fmix64((uint64_t)k) & a.mask;
         for (uint64_t t = 0; t <= a.mask; ++t) {
@@ -219,7 +245,7 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
           if (!sl.used) break;
           if (sl.key == k) {
             if (r < a.cap) {
-              a.out_idx[r] = (uint32_t)(b + u);
+              a.out_idx[r] = (uint32_t)idx[u];
               a.out_pay[r] = sl.pay;
             }
             ++r;
@@ -227,9 +253,9 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
           s = (s + 1) & a.mask;
         }
       }
-      o += cu;
     }
-    run += tot;
+    run += wpre[kProbe * kWaves];
+    __syncthreads();  // wpre is rewritten by the next round
   }
 }
 

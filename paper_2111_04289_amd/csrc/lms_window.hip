@@ -154,7 +154,8 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   const void* kc = a.q.col[a.key_col];
   const int kdt = a.q.dt[a.key_col];
-  // kHistUnroll rows per thread per step: all loads are issued before any use
+  // kHistUnroll rows per thread per step; keys are loaded only for passing
+  // rows, so a selective predicate leaves most key lines unread
   for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kHistUnroll) {
     bool ok[kHistUnroll];
     int64_t key[kHistUnroll];
@@ -163,9 +164,10 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
     for (int u = 0; u < kHistUnroll; ++u) {
       idx[u] = b + (int64_t)u * kScanTPB;
       ok[u] = idx[u] < hi;
-      key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
     }
     rows_pass<kHistUnroll>(a.q, idx, ok);
+#pragma unroll
+    for (int u = 0; u < kHistUnroll; ++u) key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
 #pragma unroll
     for (int u = 0; u < kHistUnroll; ++u)
       if (ok[u]) atomicAdd(&hist[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
@@ -331,8 +333,9 @@ __device__ __forceinline__ uint64_t staged_bits(const WinArgs& a, int v, int64_t
 }
 
 // Scatter the passing rows, as (key, pane, value columns), to their partition.
-// Every column a row needs is loaded for all kUnroll rows of a thread before
-// the first LDS cursor atomic, so the loads overlap.
+// The predicate columns are read first; every other column a passing row
+// needs is then loaded for all kUnroll rows of a thread before the first LDS
+// cursor atomic, so the loads overlap and rows that fail are never read.
 template <int MA>
 __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
@@ -353,12 +356,15 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
     for (int u = 0; u < kUnroll; ++u) {
       idx[u] = b + (int64_t)u * kScanTPB;
       ok[u] = idx[u] < hi;
+    }
+    rows_pass<kUnroll>(a.q, idx, ok);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
       key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
       ts[u] = ok[u] ? load_i64(tc, tdt, idx[u]) : 0;
 #pragma unroll
       for (int v = 0; v < MA; ++v) val[u][v] = (ok[u] && v < a.nval) ? staged_bits(a, v, idx[u]) : 0;
     }
-    rows_pass<kUnroll>(a.q, idx, ok);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (!ok[u]) continue;

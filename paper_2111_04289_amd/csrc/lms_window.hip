@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "lms_internal.h"
 
@@ -753,10 +754,36 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
     s.sorted[ks + r] = ((uint64_t)(uint32_t)q << 32) | (uint32_t)g;
   }
   __syncthreads();
+  // Permute the group arrays (id, count, accumulators) into the sorted order,
+  // one array at a time through registers, so the composition below reads a
+  // key's consecutive panes from consecutive slots instead of through the slot
+  // index.
+  {
+    constexpr int kPer = 2048 / kAggTPB;  // eg <= 2048
+    auto permute = [&](auto* arr) {
+      using T = typename std::remove_pointer<decltype(arr)>::type;
+      T v[kPer];
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const uint32_t i = threadIdx.x + t * kAggTPB;
+        if (i < ng) v[t] = arr[(uint32_t)s.sorted[i]];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < kPer; ++t) {
+        const uint32_t i = threadIdx.x + t * kAggTPB;
+        if (i < ng) arr[i] = v[t];
+      }
+      __syncthreads();
+    };
+    permute(s.gid);
+    permute(s.gcnt);
+    for (int k = 0; k < a.nacc; ++k) permute(s.acc + (size_t)k * a.eg);
+  }
   for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
     const uint64_t v = s.sorted[i];
     const int64_t q = (int64_t)(v >> 32);
-    const uint32_t kid = (uint32_t)(s.gid[(uint32_t)v] >> 32);
+    const uint32_t kid = (uint32_t)(s.gid[i] >> 32);
     const int64_t fw = first_win(q);
     const int64_t hi = last_win(q);
     int64_t lo = fw;
@@ -781,18 +808,17 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
     const int64_t idx = base + r;
     if (idx >= a.cap) continue;
     const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
-    const uint32_t kid = (uint32_t)(s.gid[(uint32_t)s.sorted[i]] >> 32);
+    const uint32_t kid = (uint32_t)(s.gid[i] >> 32);
     const uint32_t ke = s.kaux[kid] + s.kcnt[kid];
     uint32_t cnt = 0;
     uint64_t acc[MA];
 #pragma unroll
     for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
     for (uint32_t j = i; j < ke && s.fw[j] <= w; ++j) {
-      const uint32_t g = (uint32_t)s.sorted[j];
-      cnt += s.gcnt[g];
+      cnt += s.gcnt[j];
 #pragma unroll
       for (int k = 0; k < MA; ++k)
-        if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + g]);
+        if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + j]);
     }
     a.okey[idx] = key_of(a, s, kid);
     a.ows[idx] = a.origin + ((int64_t)w + wbase) * a.slide;

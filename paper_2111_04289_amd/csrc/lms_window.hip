@@ -147,6 +147,18 @@ __global__ void k_wa_init(WinArgs a) {
   if (threadIdx.x == 0) init_batch(a);
 }
 
+// Chunk processed by workgroup slot g of a launch over n chunks (slots padded
+// to a multiple of 8; a result >= n is a padding slot).  Workgroups are
+// dispatched round-robin over the 8 XCDs, so slot g runs on XCD g % 8; giving
+// each XCD a contiguous range of chunks puts neighbouring chunks -- which
+// share the cache lines of the per-(partition, chunk) count and offset arrays
+// and of each partition's staged segments -- in one XCD's L2 at about the same
+// time, so their partial-line writes merge there.
+__device__ __forceinline__ uint32_t xcd_chunk(uint32_t g, uint32_t n) {
+  const uint32_t c8 = (n + kXcds - 1) / kXcds;
+  return (g % kXcds) * c8 + g / kXcds;
+}
+
 // LDS histogram of the passing rows of chunk w over the partitions.
 __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) hist[p] = 0;
@@ -180,7 +192,9 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
 
 __global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
   extern __shared__ uint32_t hist[];
-  hist_chunk(a, blockIdx.x, hist);
+  const uint32_t w = xcd_chunk(blockIdx.x, (uint32_t)a.g1);
+  if (w >= (uint32_t)a.g1) return;
+  hist_chunk(a, w, hist);
 }
 
 // Rows per partition.
@@ -288,29 +302,20 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scanp(WinArgs a) {
 }
 
 // Per-(partition, chunk) write offsets: partition start plus an exclusive scan
-// of H[p][*] over the chunks, in XCD-major order: workgroups are dispatched
-// round-robin over the 8 XCDs, so chunks w, w+8, w+16, ... run on one XCD at
-// about the same time; placing their segments next to each other lets that
-// XCD's L2 merge the partial lines they write.
+// of H[p][*] in chunk order (neighbouring chunks run on one XCD, so their
+// segments of a partition are adjacent in that XCD's L2).
 __device__ void scan2_part(const WinArgs& a, int p, uint32_t* scratch) {
   const uint32_t start = a.pinfo[p].start;
-  const int c8 = (a.g1 + kXcds - 1) / kXcds;
-  const int nk = c8 * kXcds;
-  const int per = (nk + kScanTPB - 1) / kScanTPB;
-  const int k0 = threadIdx.x * per;
-  const int k1 = min(nk, k0 + per);
-  auto chunk_of = [&](int k) { return (k % c8) * kXcds + k / c8; };
+  const int per = (a.g1 + kScanTPB - 1) / kScanTPB;
+  const int w0 = threadIdx.x * per;
+  const int w1 = min(a.g1, w0 + per);
+  const uint32_t* h = a.H + (size_t)p * a.g1;
   uint32_t loc = 0;
-  for (int k = k0; k < k1; ++k) {
-    const int w = chunk_of(k);
-    if (w < a.g1) loc += a.H[(size_t)p * a.g1 + w];
-  }
+  for (int w = w0; w < w1; ++w) loc += h[w];
   uint32_t total;
   uint32_t run = start + block_excl_scan<kScanTPB>(loc, scratch, &total);
-  for (int k = k0; k < k1; ++k) {
-    const int w = chunk_of(k);
-    if (w >= a.g1) continue;
-    const uint32_t c = a.H[(size_t)p * a.g1 + w];
+  for (int w = w0; w < w1; ++w) {
+    const uint32_t c = h[w];
     a.Off[(size_t)p * a.g1 + w] = run;
     run += c;
   }
@@ -405,9 +410,11 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
     const uint32_t* src = (const uint32_t*)&a;
     for (uint32_t i = threadIdx.x; i < sizeof(WinArgs) / 4; i += blockDim.x) ((uint32_t*)&sa)[i] = src[i];
     __syncthreads();
-    scatter_chunk<MA>(sa, blockIdx.x, cursor);
+    const uint32_t w = xcd_chunk(blockIdx.x, (uint32_t)a.g1);
+    if (w < (uint32_t)a.g1) scatter_chunk<MA>(sa, w, cursor);
   } else {
-    scatter_chunk<MA>(a, blockIdx.x, cursor);
+    const uint32_t w = xcd_chunk(blockIdx.x, (uint32_t)a.g1);
+    if (w < (uint32_t)a.g1) scatter_chunk<MA>(a, w, cursor);
   }
 }
 
@@ -1125,10 +1132,13 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_hist(const char* desc, MultiLi
   const MultiView v = multi_view(desc);
   if (!multi_fits(v.hdr, lim)) return;
   uint32_t cur = ~0u;
-  for (uint32_t g = blockIdx.x; g < v.hdr->nchunks; g += gridDim.x) {
-    const uint32_t b = batch_of(v.cpre, v.hdr->nb, g);
+  const uint32_t n = v.hdr->nchunks, slots = (n + kXcds - 1) / kXcds * kXcds;
+  for (uint32_t g = blockIdx.x; g < slots; g += gridDim.x) {  // gridDim.x is a multiple of 8
+    const uint32_t c = xcd_chunk(g, n);
+    if (c >= n) continue;
+    const uint32_t b = batch_of(v.cpre, v.hdr->nb, c);
     load_args(v, b, &sa, &cur);
-    hist_chunk(sa, g - v.cpre[b], hist);
+    hist_chunk(sa, c - v.cpre[b], hist);
   }
 }
 
@@ -1179,10 +1189,13 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scatter(const char* desc, Mult
   const MultiView v = multi_view(desc);
   if (!multi_fits(v.hdr, lim)) return;
   uint32_t cur = ~0u;
-  for (uint32_t g = blockIdx.x; g < v.hdr->nchunks; g += gridDim.x) {
-    const uint32_t b = batch_of(v.cpre, v.hdr->nb, g);
+  const uint32_t n = v.hdr->nchunks, slots = (n + kXcds - 1) / kXcds * kXcds;
+  for (uint32_t g = blockIdx.x; g < slots; g += gridDim.x) {
+    const uint32_t c = xcd_chunk(g, n);
+    if (c >= n) continue;
+    const uint32_t b = batch_of(v.cpre, v.hdr->nb, c);
     load_args(v, b, &sa, &cur);
-    scatter_chunk<MA>(sa, g - v.cpre[b], cursor);
+    scatter_chunk<MA>(sa, c - v.cpre[b], cursor);
   }
 }
 
@@ -1254,6 +1267,9 @@ int64_t gcd64(int64_t x, int64_t y) {
 }
 
 lms_tuning g_tuning{0, 0, 0, 0, 0, 0};
+
+// Workgroup slots of a launch over n chunks (a multiple of the 8 XCDs).
+unsigned xcd_slots(int n) { return (unsigned)((n + kXcds - 1) / kXcds * kXcds); }
 
 // Bytes of a staged record for nval value columns, whatever their widths.
 size_t rec_bound(int nval) { return align_up(8 + 4 + 8 * (size_t)nval, 8); }
@@ -1394,7 +1410,7 @@ void launch_tail(const Plan& p, const WinArgs& a, size_t plds, hipStream_t st) {
     (void)hipFuncSetAttribute((const void*)k_wa_merge<MA>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
     attr_done = true;
   }
-  LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(p.g1), dim3(kScanTPB), plds, st, a);
+  LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);
   LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(p.max_items), dim3(kAggTPB), p.lds, st, a);
   LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(p.nparts), dim3(kAggTPB), p.lds, st, a);
 }
@@ -1550,7 +1566,7 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
   LMS_LAUNCH("k_wa_init", k_wa_init, dim3(1), dim3(64), 0, st, a);
   if (in->nrows > 0) {
     const size_t plds = (size_t)p.nparts * 4;
-    LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(p.g1), dim3(kScanTPB), plds, st, a);
+    LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);
     LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kScanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);

@@ -75,7 +75,8 @@ struct WinArgs {
   int32_t pbits, nparts, g1, max_items, ek, eg;
   int64_t chunk, rs;
   // workspace
-  int64_t* hdr;  // [0] base pane B0, [1] number of items
+  int64_t* hdr;  // [0] base pane B0, [1] items, [2]/[3] work counters, [4] split partitions
+  uint32_t* splits;  // nparts: the partitions split into pieces, in claim order
   uint32_t* H;
   uint32_t* Off;
   uint32_t* Rp;
@@ -133,6 +134,9 @@ __device__ __forceinline__ void init_batch(const WinArgs& a) {
     a.d_count[0] = 0;
     a.d_count[1] = 0;
     a.hdr[1] = 0;
+    a.hdr[2] = 0;  // next aggregation item to claim
+    a.hdr[3] = 0;  // next split partition to claim for merging
+    a.hdr[4] = 0;  // split partitions
     int64_t b0 = 0;
     if (a.q.nrows > 0) {
       const int64_t ts0 = load_i64(a.q.col[a.ts_col], a.q.dt[a.ts_col], 0);
@@ -291,7 +295,17 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
     a.pinfo[p].reserved = 0;
     a.pfill[p] = 0;
   }
-  if (threadIdx.x == 0) a.hdr[1] = nitems;
+  __syncthreads();
+  // list of the split partitions (the merge pass claims them one by one)
+  for (int p = threadIdx.x; p < np; p += kScanTPB) kc[p] = r[p] > rs ? 1u : 0u;
+  __syncthreads();
+  const uint32_t nsplit = block_scan_array<kScanTPB>(kc, np, scratch);
+  for (int p = threadIdx.x; p < np; p += kScanTPB)
+    if (r[p] > rs) a.splits[kc[p]] = (uint32_t)p;
+  if (threadIdx.x == 0) {
+    a.hdr[1] = nitems;
+    a.hdr[4] = nsplit;
+  }
   __syncthreads();
 }
 
@@ -1028,16 +1042,32 @@ __device__ void merge_part(const WinArgs& a, uint32_t p, char* lds_raw) {
   __syncthreads();
 }
 
+// Claims the next unit of work from a device counter (one atomic per
+// workgroup; every workgroup of the launch is resident, so claiming in order
+// balances items of unequal size).
+__device__ __forceinline__ uint32_t claim(int64_t* counter, uint32_t* slot) {
+  if (threadIdx.x == 0) *slot = (uint32_t)atomicAdd((unsigned long long*)counter, 1ull);
+  __syncthreads();
+  const uint32_t v = *slot;
+  __syncthreads();
+  return v;
+}
+
 template <int MA>
 __global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wa_agg(WinArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
-  agg_item<MA>(a, blockIdx.x, lds_raw);
+  __shared__ uint32_t slot;
+  const uint32_t n = (uint32_t)a.hdr[1];
+  for (uint32_t item = claim(&a.hdr[2], &slot); item < n; item = claim(&a.hdr[2], &slot))
+    agg_item<MA>(a, item, lds_raw);
 }
 
 template <int MA>
 __global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wa_merge(WinArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
-  merge_part<MA>(a, blockIdx.x, lds_raw);
+  __shared__ uint32_t slot;
+  const uint32_t n = (uint32_t)a.hdr[4];
+  for (uint32_t j = claim(&a.hdr[3], &slot); j < n; j = claim(&a.hdr[3], &slot)) merge_part<MA>(a, a.splits[j], lds_raw);
 }
 
 
@@ -1305,7 +1335,8 @@ Plan make_plan(int64_t n, int nval, int nacc) {
 // Carves the workspace; with base == nullptr only computes the size.
 size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   WsCarver c(base);
-  int64_t* hdr = c.take<int64_t>(4);
+  int64_t* hdr = c.take<int64_t>(8);
+  uint32_t* splits = c.take<uint32_t>(p.nparts);
   uint32_t* H = c.take<uint32_t>((size_t)p.nparts * p.g1);
   uint32_t* Off = c.take<uint32_t>((size_t)p.nparts * p.g1);
   uint32_t* Rp = c.take<uint32_t>(p.nparts);
@@ -1320,6 +1351,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   for (int k = 0; k < p.nacc; ++k) pacc[k] = c.take<uint64_t>(p.n);
   if (a) {
     a->hdr = hdr;
+    a->splits = splits;
     a->H = H;
     a->Off = Off;
     a->Rp = Rp;
@@ -1402,17 +1434,36 @@ int validate_window(const lms_batch* in, int32_t key_col, const lms_window* w) {
   return LMS_OK;
 }
 
+int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+
 template <int MA>
 void launch_tail(const Plan& p, const WinArgs& a, size_t plds, hipStream_t st) {
-  static bool attr_done = false;
-  if (!attr_done) {
-    (void)hipFuncSetAttribute((const void*)k_wa_agg<MA>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
-    (void)hipFuncSetAttribute((const void*)k_wa_merge<MA>, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit);
-    attr_done = true;
-  }
+  static const int attr_rc = [] {
+    int rc = check_hip(hipFuncSetAttribute((const void*)k_wa_agg<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsLimit - kArgsLds), "LDS attribute");
+    if (!rc)
+      rc = check_hip(hipFuncSetAttribute((const void*)k_wa_merge<MA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kLdsLimit - kArgsLds), "LDS attribute");
+    return rc;
+  }();
+  if (attr_rc) return;  // the launch error is reported by the caller's hipGetLastError
+  // the aggregation kernels claim work from counters, so they run as many
+  // workgroups as the CUs hold at once (two per CU when the tables fit twice)
+  const int per_cu = std::max(1, std::min(agg_waves(MA) / 2, (int)(kLdsLimit / (p.lds + 1024))));
+  const int resident = num_cus() * per_cu;
   LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);
-  LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(p.max_items), dim3(kAggTPB), p.lds, st, a);
-  LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(p.nparts), dim3(kAggTPB), p.lds, st, a);
+  LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(std::min(p.max_items, resident)), dim3(kAggTPB), p.lds, st, a);
+  LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(std::min(p.nparts, resident)), dim3(kAggTPB), p.lds, st, a);
 }
 
 }  // namespace
@@ -1499,17 +1550,6 @@ int setup_args(const lms_batch* in, const lms_pred* preds, int32_t npred, const 
   return LMS_OK;
 }
 
-int num_cus() {
-  static int n = 0;
-  if (n == 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-      n = v;
-    else
-      n = 256;
-  }
-  return n;
-}
 
 // Pinned staging of the multi-batch descriptors: the upload is asynchronous,
 // so the next prepare waits for the previous upload before reusing the buffer.

@@ -215,7 +215,7 @@ int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lm
  * or 0 fields select the defaults): rows per scan chunk, target rows per
  * partition, rows per aggregation piece (>= 1024), persistent scan workgroups
  * per CU, and (key, pane) slots of an aggregation workgroup's LDS table (a
- * power of two in [256, 2048], default 2048; smaller tables let two
+ * power of two in [512, 2048], default 2048; smaller tables let two
  * workgroups share a CU and lower the panes one key may hold,
  * lms_window_agg_pane_limit).  Unset partition and piece sizes default to 8
  * and 4 rows per table slot.  Chosen by the project's autotuner; results never

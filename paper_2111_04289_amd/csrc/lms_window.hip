@@ -437,7 +437,7 @@ struct Lds {
   uint64_t* keys;  // ek + 1 (slot ek holds the key equal to the empty marker)
   uint32_t* kcnt;  // ek + 1: groups per key
   uint32_t* kaux;  // ek + 1: start of the key's run in `order`
-  uint32_t* nwin;  // ek + 1: fill counter, then windows per key, then output offsets
+  uint32_t* nwin;  // ek + 1 (>= kAggTPB / 2): fill counters, then the emission rounds' row map
   uint64_t* gid;   // eg: (key slot << 32) | pane, or kEmptyGid
   uint64_t* acc;   // nacc * eg: accumulator k of group g at acc[k * eg + g]
   uint32_t* gcnt;  // eg: rows per group
@@ -450,7 +450,7 @@ struct Lds {
   uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
 };
 
-enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_WORDS = 16 };
+enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_I0 = 5, M_WORDS = 16 };
 
 __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   size_t b = 0;
@@ -726,6 +726,44 @@ __device__ __forceinline__ int64_t fdiv(int64_t x, int64_t d, double inv) {
   return q;
 }
 
+// One output row of the sliding composition: row r, owned by sorted entry i.
+template <int MA>
+__device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, uint32_t r, int64_t base,
+                                         int64_t wbase) {
+  {
+    const int64_t idx = base + r;
+    if (idx >= a.cap) return;
+    const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
+    const uint32_t kid = (uint32_t)(s.gid[i] >> 32);
+    const uint32_t ke = s.kaux[kid] + s.kcnt[kid];
+    uint32_t cnt = 0;
+    uint64_t acc[MA];
+#pragma unroll
+    for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
+    for (uint32_t j = i; j < ke && s.fw[j] <= w; ++j) {
+      cnt += s.gcnt[j];
+#pragma unroll
+      for (int k = 0; k < MA; ++k)
+        if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + j]);
+    }
+    a.okey[idx] = key_of(a, s, kid);
+    a.ows[idx] = a.origin + ((int64_t)w + wbase) * a.slide;
+    for (int k = 0; k < a.nagg; ++k) {
+      const int fn = a.afn[k];
+      if (fn == LMS_COUNT) {
+        ((int64_t*)a.oagg[k])[idx] = cnt;
+      } else {
+        const int slot = a.aacc[k];
+        uint64_t x = acc[0];
+#pragma unroll
+        for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
+        if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)x) / (double)cnt;
+        else ((int64_t*)a.oagg[k])[idx] = (int64_t)x;
+      }
+    }
+  }
+}
+
 // Sliding windows, composed in parallel over the groups of the LDS table.
 // The groups of each key are ranked by pane (every key has at most one group
 // per pane) into key-major, pane-sorted order.  Each window of a key is
@@ -818,44 +856,33 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   if (total == 0) return;
   const int64_t base = reserve_output(a, s, total);
   const int64_t wbase = b0 / a.R;
-  for (uint32_t r = threadIdx.x; r < total; r += kAggTPB) {
-    uint32_t lo = 0, hi = ng - 1;  // last entry i with order[i] <= r
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi + 1) >> 1;
-      if (s.order[mid] <= r) lo = mid;
-      else hi = mid - 1;
-    }
-    const uint32_t i = lo;
-    const int64_t idx = base + r;
-    if (idx >= a.cap) continue;
-    const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
-    const uint32_t kid = (uint32_t)(s.gid[i] >> 32);
-    const uint32_t ke = s.kaux[kid] + s.kcnt[kid];
-    uint32_t cnt = 0;
-    uint64_t acc[MA];
-#pragma unroll
-    for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
-    for (uint32_t j = i; j < ke && s.fw[j] <= w; ++j) {
-      cnt += s.gcnt[j];
-#pragma unroll
-      for (int k = 0; k < MA; ++k)
-        if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + j]);
-    }
-    a.okey[idx] = key_of(a, s, kid);
-    a.ows[idx] = a.origin + ((int64_t)w + wbase) * a.slide;
-    for (int k = 0; k < a.nagg; ++k) {
-      const int fn = a.afn[k];
-      if (fn == LMS_COUNT) {
-        ((int64_t*)a.oagg[k])[idx] = cnt;
-      } else {
-        const int slot = a.aacc[k];
-        uint64_t x = acc[0];
-#pragma unroll
-        for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
-        if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)x) / (double)cnt;
-        else ((int64_t*)a.oagg[k])[idx] = (int64_t)x;
+  // Rows go out in rounds of kAggTPB, one per thread.  Per round, the entries
+  // overlapping it mark their rows in an LDS row map (found from the round's
+  // first entry, one search per round), so each thread reads its entry
+  // directly instead of searching for it.
+  uint16_t* const rmap = (uint16_t*)s.nwin;  // kAggTPB entries; the fill counters are no longer needed
+  static_assert(kAggTPB * 2 <= (512 / 2 + 1) * 4, "row map must fit the smallest key table");
+  for (uint32_t r0 = 0; r0 < total; r0 += kAggTPB) {
+    if (threadIdx.x == 0) {
+      uint32_t lo = 0, hi = ng - 1;  // last entry i with order[i] <= r0
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s.order[mid] <= r0) lo = mid;
+        else hi = mid - 1;
       }
+      s.misc[M_I0] = lo;
     }
+    __syncthreads();
+    const uint32_t r1 = min(total, r0 + (uint32_t)kAggTPB);
+    for (uint32_t e = s.misc[M_I0] + threadIdx.x; e < ng && s.order[e] < r1; e += kAggTPB) {
+      const uint32_t a0 = max(s.order[e], r0);
+      const uint32_t a1 = min(e + 1 < ng ? s.order[e + 1] : total, r1);
+      for (uint32_t rr = a0; rr < a1; ++rr) rmap[rr - r0] = (uint16_t)e;
+    }
+    __syncthreads();
+    const uint32_t r = r0 + threadIdx.x;
+    if (r < r1) emit_row<MA>(a, s, rmap[threadIdx.x], r, base, wbase);
+    __syncthreads();  // the row map is rewritten by the next round
   }
 }
 
@@ -1628,8 +1655,8 @@ extern "C" int lms_set_tuning(const lms_tuning* t) {
   if (t->chunk_rows < 0 || t->part_rows < 0 || t->piece_rows < 0 || t->grid_per_cu < 0 || t->lds_groups < 0)
     return set_error(LMS_EINVAL, "tuning values must be >= 0");
   if (t->piece_rows > 0 && t->piece_rows < 1024) return set_error(LMS_EINVAL, "piece_rows must be >= 1024");
-  if (t->lds_groups != 0 && (t->lds_groups < 256 || t->lds_groups > 2048 || (t->lds_groups & (t->lds_groups - 1))))
-    return set_error(LMS_EINVAL, "lds_groups must be 0 or a power of two in [256, 2048]");
+  if (t->lds_groups != 0 && (t->lds_groups < 512 || t->lds_groups > 2048 || (t->lds_groups & (t->lds_groups - 1))))
+    return set_error(LMS_EINVAL, "lds_groups must be 0 or a power of two in [512, 2048]");
   g_tuning = *t;
   return LMS_OK;
 }

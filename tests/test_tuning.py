@@ -18,7 +18,7 @@ def test_set_get_roundtrip_and_reset():
 
 
 @pytest.mark.parametrize("bad", [dict(chunk_rows=-1), dict(piece_rows=512), dict(grid_per_cu=-2),
-                                 dict(lds_groups=768), dict(lds_groups=4096), dict(lds_groups=128)])
+                                 dict(lds_groups=768), dict(lds_groups=4096), dict(lds_groups=256)])
 def test_invalid_tuning_rejected(bad):
     with pytest.raises(lms.LmsError) as e:
         lms.set_tuning(**bad)

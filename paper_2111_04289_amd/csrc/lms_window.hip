@@ -734,17 +734,30 @@ __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, u
     const int64_t idx = base + r;
     if (idx >= a.cap) return;
     const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
-    const uint32_t kid = (uint32_t)(s.gid[i] >> 32);
-    const uint32_t ke = s.kaux[kid] + s.kcnt[kid];
+    const uint64_t kk = s.sorted[i];
+    const uint32_t kid = (uint32_t)kk, ke = (uint32_t)(kk >> 32);
     uint32_t cnt = 0;
     uint64_t acc[MA];
 #pragma unroll
     for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
-    for (uint32_t j = i; j < ke && s.fw[j] <= w; ++j) {
-      cnt += s.gcnt[j];
+    // the window's panes are the key's entries from i on whose first window is
+    // not after w; four entries are loaded per step, so the LDS round trips of
+    // a step overlap instead of each waiting on the previous test
+    constexpr int kStep = MA <= 6 ? 4 : 1;  // the widest unroll's registers would spill
+    for (uint32_t j = i; j < ke; j += kStep) {
+      bool more = true;
 #pragma unroll
-      for (int k = 0; k < MA; ++k)
-        if (k < a.nacc) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + j]);
+      for (int u = 0; u < kStep; ++u) {
+        const uint32_t jj = j + u;
+        const bool ok = jj < ke;
+        const bool in = ok && s.fw[jj] <= w;
+        cnt += in ? s.gcnt[jj] : 0u;
+#pragma unroll
+        for (int k = 0; k < MA; ++k)
+          if (k < a.nacc && in) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + jj]);
+        more = in;
+      }
+      if (!more) break;
     }
     a.okey[idx] = key_of(a, s, kid);
     a.ows[idx] = a.origin + ((int64_t)w + wbase) * a.slide;
@@ -853,6 +866,13 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   }
   __syncthreads();
   const uint32_t total = block_scan_array<kAggTPB>(s.order, (int)ng, s.scan);  // order = first row of entry
+  // the panes are no longer needed: each entry keeps its key slot and the end
+  // of its key's run instead, so a row finds both with one load
+  for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
+    const uint32_t kid = (uint32_t)(s.gid[i] >> 32);
+    s.sorted[i] = ((uint64_t)(s.kaux[kid] + s.kcnt[kid]) << 32) | kid;
+  }
+  __syncthreads();
   if (total == 0) return;
   const int64_t base = reserve_output(a, s, total);
   const int64_t wbase = b0 / a.R;

@@ -35,11 +35,11 @@ namespace {
 
 constexpr int kScanTPB = 256;
 constexpr int kAggTPB = 512;
-// Waves per SIMD the aggregation kernels are compiled for: 4 (<= 128 VGPRs)
-// lets two 512-thread workgroups share a CU when their LDS tables fit
-// (lds_groups 1024); with more than 4 accumulators that would spill, so those
-// instances keep the register budget of 2.
-constexpr int agg_waves(int ma) { return ma <= 4 ? 4 : 2; }
+// Waves per SIMD the aggregation kernels are compiled for.  One 512-thread
+// workgroup per CU (2 waves per SIMD) is what the default 2048-slot LDS tables
+// allow, and measured tuning keeps those tables; a budget of 2 leaves the
+// registers for the unrolled loads of the composition without spilling.
+constexpr int agg_waves(int) { return 2; }
 constexpr uint64_t kEmptyKey = 0x8000000000000000ull;
 constexpr uint64_t kEmptyGid = ~0ull;
 constexpr int kLdsLimit = 160 * 1024;
@@ -695,7 +695,11 @@ __device__ void emit_tumbling(const WinArgs& a, Lds& s, int64_t b0) {
         const uint32_t cnt = s.gcnt[g];
         a.okey[idx] = key_of(a, s, (uint32_t)(gid >> 32));
         a.ows[idx] = a.origin + (b0 + (int64_t)(uint32_t)gid) * a.len;
-        for (int k = 0; k < a.nagg; ++k) {
+        // unrolled over the aggregate bound so each aggregate's function, slot and
+        // output pointer are compile-time kernel-argument offsets (scalar registers)
+#pragma unroll
+        for (int k = 0; k < kMaxAggs; ++k) {
+          if (k >= a.nagg) break;
           const int fn = a.afn[k];
           if (fn == LMS_COUNT) {
             ((int64_t*)a.oagg[k])[idx] = cnt;
@@ -761,7 +765,10 @@ __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, u
     }
     a.okey[idx] = key_of(a, s, kid);
     a.ows[idx] = a.origin + ((int64_t)w + wbase) * a.slide;
-    for (int k = 0; k < a.nagg; ++k) {
+    // unrolled over the aggregate bound: compile-time kernel-argument offsets
+#pragma unroll
+    for (int k = 0; k < kMaxAggs; ++k) {
+      if (k >= a.nagg) break;
       const int fn = a.afn[k];
       if (fn == LMS_COUNT) {
         ((int64_t*)a.oagg[k])[idx] = cnt;

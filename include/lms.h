@@ -214,10 +214,9 @@ int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lm
 /* Tile and schedule parameters of the windowed group-by (process-wide; NULL
  * or 0 fields select the defaults): rows per scan chunk, target rows per
  * partition, rows per aggregation piece (>= 1024), persistent scan workgroups
- * per CU, and (key, pane) slots of an aggregation workgroup's LDS table (a
- * power of two in [512, 2048], default 2048; smaller tables let two
- * workgroups share a CU and lower the panes one key may hold,
- * lms_window_agg_pane_limit).  Unset partition and piece sizes default to 8
+ * per CU, and (key, pane) slots of an aggregation workgroup's LDS table (1024
+ * or 2048, the default; the smaller table fits two workgroups' LDS in a CU
+ * and lowers the panes one key may hold, lms_window_agg_pane_limit).  Unset partition and piece sizes default to 8
  * and 4 rows per table slot.  Chosen by the project's autotuner; results never
  * depend on them. */
 typedef struct {

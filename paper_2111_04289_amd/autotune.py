@@ -30,7 +30,7 @@ PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json"
 
 SPACE = {
     "chunk_rows": [0, 2048, 8192, 32768, 65536],
-    "lds_groups": [0, 1024, 512],
+    "lds_groups": [0, 1024],
     "part_rows": [0, 4096, 8192, 32768],
     "piece_rows": [0, 2048, 4096, 16384],
     "grid_per_cu": [0, 2, 8],

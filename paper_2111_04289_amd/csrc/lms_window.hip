@@ -34,12 +34,11 @@ namespace lms {
 namespace {
 
 constexpr int kScanTPB = 256;
-constexpr int kAggTPB = 512;
-// Waves per SIMD the aggregation kernels are compiled for.  One 512-thread
-// workgroup per CU (2 waves per SIMD) is what the default 2048-slot LDS tables
-// allow, and measured tuning keeps those tables; a budget of 2 leaves the
-// registers for the unrolled loads of the composition without spilling.
-constexpr int agg_waves(int) { return 2; }
+constexpr int kAggTPB = 1024;
+// Waves per SIMD the aggregation kernels are compiled for: one 1024-thread
+// workgroup per CU (what the default 2048-slot LDS tables allow) is 4 waves
+// per SIMD, so more independent LDS chains are in flight while each waits.
+constexpr int agg_waves(int) { return 4; }
 constexpr uint64_t kEmptyKey = 0x8000000000000000ull;
 constexpr uint64_t kEmptyGid = ~0ull;
 constexpr int kLdsLimit = 160 * 1024;
@@ -747,7 +746,7 @@ __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, u
     // the window's panes are the key's entries from i on whose first window is
     // not after w; four entries are loaded per step, so the LDS round trips of
     // a step overlap instead of each waiting on the previous test
-    constexpr int kStep = MA <= 6 ? 4 : 1;  // the widest unroll's registers would spill
+    constexpr int kStep = MA <= 2 ? 4 : MA <= 4 ? 2 : 1;  // wider unrolls would spill
     for (uint32_t j = i; j < ke; j += kStep) {
       bool more = true;
 #pragma unroll
@@ -888,7 +887,7 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   // first entry, one search per round), so each thread reads its entry
   // directly instead of searching for it.
   uint16_t* const rmap = (uint16_t*)s.nwin;  // kAggTPB entries; the fill counters are no longer needed
-  static_assert(kAggTPB * 2 <= (512 / 2 + 1) * 4, "row map must fit the smallest key table");
+  static_assert(kAggTPB * 2 <= (1024 / 2 + 1) * 4, "row map must fit the smallest key table");
   for (uint32_t r0 = 0; r0 < total; r0 += kAggTPB) {
     if (threadIdx.x == 0) {
       uint32_t lo = 0, hi = ng - 1;  // last entry i with order[i] <= r0
@@ -1512,9 +1511,9 @@ void launch_tail(const Plan& p, const WinArgs& a, size_t plds, hipStream_t st) {
   }();
   if (attr_rc) return;  // the launch error is reported by the caller's hipGetLastError
   // the aggregation kernels claim work from counters, so they run as many
-  // workgroups as the CUs hold at once (two per CU when the tables fit twice)
-  const int per_cu = std::max(1, std::min(agg_waves(MA) / 2, (int)(kLdsLimit / (p.lds + 1024))));
-  const int resident = num_cus() * per_cu;
+  // workgroups as the CUs hold at once: one per CU (a 1024-thread workgroup
+  // already fills each SIMD's register budget at 4 waves)
+  const int resident = num_cus();
   LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);
   LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(std::min(p.max_items, resident)), dim3(kAggTPB), p.lds, st, a);
   LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(std::min(p.nparts, resident)), dim3(kAggTPB), p.lds, st, a);
@@ -1682,8 +1681,8 @@ extern "C" int lms_set_tuning(const lms_tuning* t) {
   if (t->chunk_rows < 0 || t->part_rows < 0 || t->piece_rows < 0 || t->grid_per_cu < 0 || t->lds_groups < 0)
     return set_error(LMS_EINVAL, "tuning values must be >= 0");
   if (t->piece_rows > 0 && t->piece_rows < 1024) return set_error(LMS_EINVAL, "piece_rows must be >= 1024");
-  if (t->lds_groups != 0 && (t->lds_groups < 512 || t->lds_groups > 2048 || (t->lds_groups & (t->lds_groups - 1))))
-    return set_error(LMS_EINVAL, "lds_groups must be 0 or a power of two in [512, 2048]");
+  if (t->lds_groups != 0 && (t->lds_groups < 1024 || t->lds_groups > 2048 || (t->lds_groups & (t->lds_groups - 1))))
+    return set_error(LMS_EINVAL, "lds_groups must be 0, 1024 or 2048");
   g_tuning = *t;
   return LMS_OK;
 }

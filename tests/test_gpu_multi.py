@@ -125,7 +125,7 @@ def test_multi_graph_replay(lms):
 
 
 @pytest.mark.parametrize("tuning", [dict(chunk_rows=2048, part_rows=8192, piece_rows=1024, grid_per_cu=1,
-                                         lds_groups=512),
+                                         lds_groups=1024),
                                     dict(chunk_rows=65536, part_rows=65536, piece_rows=32768, grid_per_cu=8)])
 def test_tuning_keeps_results(lms, tuning):
     """Tile and schedule parameters change the work split, never the result."""

@@ -9,16 +9,16 @@ from paper_2111_04289_amd import autotune  # noqa: E402
 
 
 def test_set_get_roundtrip_and_reset():
-    lms.set_tuning(chunk_rows=4096, part_rows=8192, piece_rows=2048, grid_per_cu=3, lds_groups=512)
+    lms.set_tuning(chunk_rows=4096, part_rows=8192, piece_rows=2048, grid_per_cu=3, lds_groups=1024)
     assert lms.get_tuning() == {"chunk_rows": 4096, "part_rows": 8192, "piece_rows": 2048, "grid_per_cu": 3,
-                                "lds_groups": 512}
-    assert lms.pane_limit(4) == 512
+                                "lds_groups": 1024}
+    assert lms.pane_limit(4) == 1024
     lms.set_tuning()
     assert lms.get_tuning() == {"chunk_rows": 0, "part_rows": 0, "piece_rows": 0, "grid_per_cu": 0, "lds_groups": 0}
 
 
 @pytest.mark.parametrize("bad", [dict(chunk_rows=-1), dict(piece_rows=512), dict(grid_per_cu=-2),
-                                 dict(lds_groups=768), dict(lds_groups=4096), dict(lds_groups=256)])
+                                 dict(lds_groups=768), dict(lds_groups=4096), dict(lds_groups=512)])
 def test_invalid_tuning_rejected(bad):
     with pytest.raises(lms.LmsError) as e:
         lms.set_tuning(**bad)

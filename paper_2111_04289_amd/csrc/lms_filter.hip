@@ -94,6 +94,7 @@ __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t below = (1ull << lane) - 1;
   int64_t run = a.tile_off[blockIdx.x];
+  const bool dense = a.tile_cnt[blockIdx.x] * 8 >= hi - lo;
   for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kRows) {
     int64_t idx[kRows];
     bool pass[kRows];
@@ -123,10 +124,17 @@ __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
     int64_t r[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) r[u] = run + wpre[u * kWaves + wave] + __popcll(m[u] & below);
+    // per column, the rows' values are loaded together before any is stored, so
+    // the loads of a round overlap; a dense tile (at least one row in eight
+    // passing, so nearly every cache line is needed anyway) loads every row
+    // without waiting on the predicate, a sparse one only the passing rows
     for (int j = 0; j < ncol; ++j) {
+      uint64_t v[kRows];
+#pragma unroll
+      for (int u = 0; u < kRows; ++u) v[u] = ((dense && idx[u] < hi) || pass[u]) ? out_bits(a, j, idx[u]) : 0;
 #pragma unroll
       for (int u = 0; u < kRows; ++u)
-        if (pass[u]) put_bits(a.out[j], a.odt[j], r[u], out_bits(a, j, idx[u]));
+        if (pass[u]) put_bits(a.out[j], a.odt[j], r[u], v[u]);
     }
     run += wpre[kRows * kWaves];
     __syncthreads();  // wpre is rewritten by the next round

@@ -436,7 +436,7 @@ struct Lds {
   uint64_t* keys;  // ek + 1 (slot ek holds the key equal to the empty marker)
   uint32_t* kcnt;  // ek + 1: groups per key
   uint32_t* kaux;  // ek + 1: start of the key's run in `order`
-  uint32_t* nwin;  // ek + 1 (>= kAggTPB / 2): fill counters, then the emission rounds' row map
+  uint32_t* nwin;  // ek + 1: fill counters of the counting sort
   uint64_t* gid;   // eg: (key slot << 32) | pane, or kEmptyGid
   uint64_t* acc;   // nacc * eg: accumulator k of group g at acc[k * eg + g]
   uint32_t* gcnt;  // eg: rows per group
@@ -449,7 +449,7 @@ struct Lds {
   uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
 };
 
-enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_I0 = 5, M_WORDS = 16 };
+enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_WORDS = 16 };
 
 __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   size_t b = 0;
@@ -882,33 +882,36 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   if (total == 0) return;
   const int64_t base = reserve_output(a, s, total);
   const int64_t wbase = b0 / a.R;
-  // Rows go out in rounds of kAggTPB, one per thread.  Per round, the entries
-  // overlapping it mark their rows in an LDS row map (found from the round's
-  // first entry, one search per round), so each thread reads its entry
-  // directly instead of searching for it.
-  uint16_t* const rmap = (uint16_t*)s.nwin;  // kAggTPB entries; the fill counters are no longer needed
-  static_assert(kAggTPB * 2 <= (1024 / 2 + 1) * 4, "row map must fit the smallest key table");
-  for (uint32_t r0 = 0; r0 < total; r0 += kAggTPB) {
-    if (threadIdx.x == 0) {
+  // Rows go out in blocks of 64, one per lane, each wave taking every
+  // (kAggTPB / 64)-th block.  Lane 0 finds the block's first entry and
+  // broadcasts it; every lane then searches only the block's entries (at most
+  // 64 R of them, as each owned window spans at most R panes).  Nothing here
+  // needs a workgroup barrier, so a wave's output stores overlap its next
+  // block instead of being waited for.
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t span = (uint32_t)min<int64_t>(64 * a.R, ng);
+  for (uint32_t r0 = (threadIdx.x >> 6) * 64; r0 < total; r0 += kAggTPB) {
+    uint32_t i0 = 0;
+    if (lane == 0) {
       uint32_t lo = 0, hi = ng - 1;  // last entry i with order[i] <= r0
       while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
         if (s.order[mid] <= r0) lo = mid;
         else hi = mid - 1;
       }
-      s.misc[M_I0] = lo;
+      i0 = lo;
     }
-    __syncthreads();
-    const uint32_t r1 = min(total, r0 + (uint32_t)kAggTPB);
-    for (uint32_t e = s.misc[M_I0] + threadIdx.x; e < ng && s.order[e] < r1; e += kAggTPB) {
-      const uint32_t a0 = max(s.order[e], r0);
-      const uint32_t a1 = min(e + 1 < ng ? s.order[e + 1] : total, r1);
-      for (uint32_t rr = a0; rr < a1; ++rr) rmap[rr - r0] = (uint16_t)e;
+    i0 = (uint32_t)__shfl((int)i0, 0, 64);
+    const uint32_t r = r0 + lane;
+    if (r < total) {
+      uint32_t lo = i0, hi = min(ng - 1, i0 + span);  // last entry i with order[i] <= r
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (s.order[mid] <= r) lo = mid;
+        else hi = mid - 1;
+      }
+      emit_row<MA>(a, s, lo, r, base, wbase);
     }
-    __syncthreads();
-    const uint32_t r = r0 + threadIdx.x;
-    if (r < r1) emit_row<MA>(a, s, rmap[threadIdx.x], r, base, wbase);
-    __syncthreads();  // the row map is rewritten by the next round
   }
 }
 

@@ -1,11 +1,11 @@
 // Filtering + Projection (Table II rows "Filtering" and "Projection"): stable
 // stream compaction of the rows that pass a conjunction of predicates.
 //
-// Three launches: per-tile counts of passing rows, one scan of the tile
-// counts, then a write pass that ranks each round of rows with wave ballots
-// and a block prefix, so rows keep their input order without any global
-// atomic, and both the column loads and the output writes are contiguous per
-// wave.
+// Three launches: per-tile counts of passing rows (a tile is one wave's
+// contiguous range), one scan of the tile counts, then a write pass that ranks
+// rows with wave ballots and a running count, so rows keep their input order
+// without any global atomic or workgroup barrier, and both the column loads
+// and the output writes are contiguous per wave.
 #include <algorithm>
 
 #include "lms_internal.h"
@@ -30,28 +30,34 @@ struct FpArgs {
   int64_t* d_count;
 };
 
-// A round is kRows sub-rounds of kTPB consecutive rows; in sub-round u lane t
-// takes row b0 + u * kTPB + t, so every column load of a wave is one
-// contiguous run.
+// Tiles belong to waves: wave tile t covers rows [t * chunk, (t + 1) * chunk)
+// (chunk = kWaveRows), processed in rounds of kRows sub-rounds of 64
+// consecutive rows with lane l on row b0 + u * 64 + l, so every column load of
+// a wave is one contiguous run and no workgroup-level step is needed.
+constexpr int kWaveRows = 64 * kRows * 4;
+
+__device__ __forceinline__ int64_t wave_tile() { return ((int64_t)blockIdx.x * kTPB + threadIdx.x) >> 6; }
+
 __global__ __launch_bounds__(kTPB) void k_fp_count(FpArgs a) {
-  __shared__ uint32_t scratch[kTPB / 64 + 1];
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t t = wave_tile();
+  if (t >= a.ntiles) return;
+  const int64_t lo = t * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
+  const int lane = threadIdx.x & 63;
   uint32_t c = 0;
-  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kRows) {
+  for (int64_t b0 = lo; b0 < hi; b0 += 64 * kRows) {
     int64_t idx[kRows];
     bool ok[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) {
-      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
+      idx[u] = b0 + (int64_t)u * 64 + lane;
       ok[u] = idx[u] < hi;
     }
     rows_pass<kRows>(a.q, idx, ok);
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) c += ok[u] ? 1u : 0u;
+    for (int u = 0; u < kRows; ++u) c += (uint32_t)__popcll(__ballot(ok[u]));
   }
-  c = block_sum<kTPB>(c, scratch);
-  if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = c;
+  if (lane == 0) a.tile_cnt[t] = c;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_fp_scan(FpArgs a) {
@@ -80,54 +86,40 @@ __device__ __forceinline__ void put_bits(void* col, int dt, int64_t r, uint64_t 
   else ((uint64_t*)col)[r] = v;
 }
 
-// Stable compaction.  Ranks come from wave ballots: a passing row's rank is
-// the passing rows of earlier (sub-round, wave) pairs -- sub-round major, as
-// rows are ordered -- plus those of lower lanes in its wave's ballot.  The
-// passing lanes of a wave therefore write one contiguous run of each output
-// column, and every load is contiguous too; no value is staged.
+// Stable compaction, one wave per tile: a passing row's output position is the
+// tile's offset, plus the passing rows of the wave's earlier sub-rounds (a
+// running count), plus those of lower lanes in its sub-round's ballot.  The
+// passing lanes of a sub-round write one contiguous run of each column.  No
+// workgroup barrier: a wave's stores drain while it moves on.
 __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
-  constexpr int kWaves = kTPB / 64;
-  __shared__ uint32_t wpre[kRows * kWaves + 1];
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t t = wave_tile();
+  if (t >= a.ntiles) return;
+  const int64_t lo = t * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   const int ncol = a.nkeep + a.q.nproj;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   const uint64_t below = (1ull << lane) - 1;
-  int64_t run = a.tile_off[blockIdx.x];
-  const bool dense = a.tile_cnt[blockIdx.x] * 8 >= hi - lo;
-  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kRows) {
+  // a dense tile (at least one row in eight passing, so nearly every cache
+  // line is needed anyway) loads every row's values without waiting on the
+  // predicate; a sparse one only the passing rows'
+  const bool dense = a.tile_cnt[t] * 8 >= hi - lo;
+  int64_t run = a.tile_off[t];
+  for (int64_t b0 = lo; b0 < hi; b0 += 64 * kRows) {
     int64_t idx[kRows];
     bool pass[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) {
-      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
+      idx[u] = b0 + (int64_t)u * 64 + lane;
       pass[u] = idx[u] < hi;
     }
     rows_pass<kRows>(a.q, idx, pass);
-    uint64_t m[kRows];
-#pragma unroll
-    for (int u = 0; u < kRows; ++u) {
-      m[u] = __ballot(pass[u]);
-      if (lane == 0) wpre[u * kWaves + wave] = (uint32_t)__popcll(m[u]);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t t = 0;
-      for (int i = 0; i < kRows * kWaves; ++i) {
-        const uint32_t v = wpre[i];
-        wpre[i] = t;
-        t += v;
-      }
-      wpre[kRows * kWaves] = t;
-    }
-    __syncthreads();
     int64_t r[kRows];
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) r[u] = run + wpre[u * kWaves + wave] + __popcll(m[u] & below);
-    // per column, the rows' values are loaded together before any is stored, so
-    // the loads of a round overlap; a dense tile (at least one row in eight
-    // passing, so nearly every cache line is needed anyway) loads every row
-    // without waiting on the predicate, a sparse one only the passing rows
+    for (int u = 0; u < kRows; ++u) {
+      const uint64_t m = __ballot(pass[u]);
+      r[u] = run + __popcll(m & below);
+      run += __popcll(m);
+    }
     for (int j = 0; j < ncol; ++j) {
       uint64_t v[kRows];
 #pragma unroll
@@ -136,8 +128,6 @@ __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
       for (int u = 0; u < kRows; ++u)
         if (pass[u]) put_bits(a.out[j], a.odt[j], r[u], v[u]);
     }
-    run += wpre[kRows * kWaves];
-    __syncthreads();  // wpre is rewritten by the next round
   }
 }
 
@@ -155,8 +145,8 @@ struct FpPlan {
 
 FpPlan fp_plan(int64_t n) {
   FpPlan p;
-  p.chunk = 8192;  // measured: larger tiles serialise the rounds of a workgroup and run slower
-  while ((n + p.chunk - 1) / p.chunk > 65536) p.chunk *= 2;
+  p.chunk = kWaveRows;
+  while ((n + p.chunk - 1) / p.chunk > (1 << 20)) p.chunk *= 2;  // at most 2^20 wave tiles
   p.ntiles = (int)((n + p.chunk - 1) / p.chunk);
   return p;
 }
@@ -220,9 +210,10 @@ extern "C" int lms_filter_project(const lms_batch* in, const lms_pred* preds, in
   if (in->nrows == 0) {
     LMS_LAUNCH("k_fp_empty", k_fp_empty, dim3(1), dim3(64), 0, st, a);
   } else {
-    LMS_LAUNCH("k_fp_count", k_fp_count, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+    const unsigned wgs = (unsigned)((p.ntiles + kTPB / 64 - 1) / (kTPB / 64));  // one wave per tile
+    LMS_LAUNCH("k_fp_count", k_fp_count, dim3(wgs), dim3(kTPB), 0, st, a);
     LMS_LAUNCH("k_fp_scan", k_fp_scan, dim3(1), dim3(kScanThreads), 0, st, a);
-    LMS_LAUNCH("k_fp_write", k_fp_write, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+    LMS_LAUNCH("k_fp_write", k_fp_write, dim3(wgs), dim3(kTPB), 0, st, a);
   }
   return check_hip(hipGetLastError(), "filter_project launch");
 }

@@ -7,11 +7,11 @@
 // lie in the run of used slots that starts at its home slot, so a probe walks
 // from the home slot to the first unused slot.
 // Probe: one pass walks the chains and records each row's match count and
-// first payload (8 bytes per row, coalesced) with per-tile totals; a scan of
-// the tile counts; then a write pass that ranks each round of rows with a
-// block prefix, so the pairs come out grouped by ascending probe row without
-// global atomics, and touches the table again only for rows with several
-// matches.  Each thread walks the chains of several consecutive rows in
+// first payload (8 bytes per row, coalesced) with per-tile totals (a tile is
+// one wave's contiguous range); a scan of the tile counts; then a write pass
+// that ranks rows with a wave scan and a running offset, so the pairs come out
+// grouped by ascending probe row without global atomics or workgroup
+// barriers, and touches the table again only for rows with several matches.  Each thread walks the chains of several consecutive rows in
 // lockstep to overlap the random slot reads (the table is MALL-resident, not
 // L2-resident).
 #include <algorithm>
@@ -138,24 +138,38 @@ __device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)
   }
 }
 
+// Tiles belong to waves: wave tile t covers rows [t * chunk, (t + 1) * chunk),
+// processed in rounds of kProbe sub-rounds of 64 consecutive rows with lane l
+// on row b0 + u * 64 + l, so key loads and record stores are contiguous per
+// wave, and no step needs a workgroup barrier.
+constexpr int kWaveRows = 64 * kProbe * 8;
+
+__device__ __forceinline__ int64_t wave_tile() { return ((int64_t)blockIdx.x * kTPB + threadIdx.x) >> 6; }
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += (uint32_t)__shfl_xor((int)v, d, 64);
+  return v;
+}
+
 // Probe pass: walks every row's chain once and records, per row, its match
 // count and first payload (packed count << 32 | payload) for the write pass,
-// plus the tile's total.  A round is kProbe sub-rounds of kTPB consecutive
-// rows; lane t takes row b0 + u * kTPB + t of sub-round u, so key loads and
-// record stores are contiguous per wave.
+// plus the wave tile's total.
 __global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
-  __shared__ uint32_t scratch[kTPB / 64 + 1];
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t t = wave_tile();
+  if (t >= a.ntiles) return;
+  const int64_t lo = t * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
+  const int lane = threadIdx.x & 63;
   uint32_t c = 0;
-  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kProbe) {
+  for (int64_t b0 = lo; b0 < hi; b0 += 64 * kProbe) {
     int64_t k[kProbe], idx[kProbe];
     bool valid[kProbe];
     uint32_t cnt[kProbe];
     uint32_t first[kProbe];
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
-      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
+      idx[u] = b0 + (int64_t)u * 64 + lane;
       valid[u] = idx[u] < hi;
       k[u] = valid[u] ? load_i64(a.pkey, a.kdt, idx[u]) : 0;
       cnt[u] = 0;
@@ -171,8 +185,8 @@ __global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
       c += cnt[u];
     }
   }
-  c = block_sum<kTPB>(c, scratch);
-  if (threadIdx.x == 0) a.tile_cnt[blockIdx.x] = c;
+  c = wave_sum(c);
+  if (lane == 0) a.tile_cnt[t] = c;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_jp_scan(ProbeArgs a) {
@@ -185,52 +199,38 @@ __global__ __launch_bounds__(kScanThreads) void k_jp_scan(ProbeArgs a) {
   }
 }
 
-// Write pass: reads the recorded hits (no table access for rows with at most
-// one match) in the probe pass's row layout and ranks the pairs in row order:
-// a wave scan of the match counts plus a block prefix over (sub-round, wave)
-// totals, sub-round major.  The pairs come out grouped by ascending probe row;
-// a row with several matches walks its chain again, in the same order.
+// Write pass, one wave per tile: reads the recorded hits (no table access for
+// rows with at most one match) and ranks the pairs in row order with a wave
+// scan of the match counts and a running offset.  The pairs come out grouped
+// by ascending probe row; a row with several matches walks its chain again,
+// in the same order.
 __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
-  constexpr int kWaves = kTPB / 64;
-  __shared__ uint32_t wpre[kProbe * kWaves + 1];
-  const int64_t lo = (int64_t)blockIdx.x * a.chunk;
+  const int64_t t = wave_tile();
+  if (t >= a.ntiles) return;
+  const int64_t lo = t * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int64_t run = a.tile_off[blockIdx.x];
-  for (int64_t b0 = lo; b0 < hi; b0 += (int64_t)kTPB * kProbe) {
+  const int lane = threadIdx.x & 63;
+  int64_t run = a.tile_off[t];
+  for (int64_t b0 = lo; b0 < hi; b0 += 64 * kProbe) {
     int64_t idx[kProbe];
     uint64_t h[kProbe];
-    uint32_t ex[kProbe];
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
-      idx[u] = b0 + (int64_t)u * kTPB + threadIdx.x;
+      idx[u] = b0 + (int64_t)u * 64 + lane;
       h[u] = idx[u] < hi ? a.hits[idx[u]] : 0;
-      const uint32_t v = (uint32_t)(h[u] >> 32);
-      uint32_t x = v;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-      }
-      ex[u] = x - v;
-      if (lane == 63) wpre[u * kWaves + wave] = x;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      uint32_t t = 0;
-      for (int i = 0; i < kProbe * kWaves; ++i) {
-        const uint32_t v = wpre[i];
-        wpre[i] = t;
-        t += v;
-      }
-      wpre[kProbe * kWaves] = t;
-    }
-    __syncthreads();
 #pragma unroll
     for (int u = 0; u < kProbe; ++u) {
       const uint32_t cu = (uint32_t)(h[u] >> 32);
+      uint32_t x = cu;  // inclusive scan over the wave
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+        if (lane >= d) x += y;
+      }
+      const int64_t o = run + (x - cu);
+      run += (uint32_t)__shfl((int)x, 63, 64);
       if (cu == 0) continue;
-      const int64_t o = run + wpre[u * kWaves + wave] + ex[u];
       if (cu == 1) {
         if (o < a.cap) {
           a.out_idx[o] = (uint32_t)idx[u];
@@ -239,9 +239,9 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
       } else {
         const int64_t k = load_i64(a.pkey, a.kdt, idx[u]);
         int64_t r = o;
-        uint64_t s = fmix64((uint64_t)k) & a.mask;
-        for (uint64_t t = 0; t <= a.mask; ++t) {
-          const JSlot sl = a.slots[s];
+        uint64_t sl_i = fmix64((uint64_t)k) & a.mask;
+        for (uint64_t q = 0; q <= a.mask; ++q) {
+          const JSlot sl = a.slots[sl_i];
           if (!sl.used) break;
           if (sl.key == k) {
             if (r < a.cap) {
@@ -250,12 +250,10 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
             }
             ++r;
           }
-          s = (s + 1) & a.mask;
+          sl_i = (sl_i + 1) & a.mask;
         }
       }
     }
-    run += wpre[kProbe * kWaves];
-    __syncthreads();  // wpre is rewritten by the next round
   }
 }
 
@@ -273,8 +271,8 @@ struct JpPlan {
 
 JpPlan jp_plan(int64_t n) {
   JpPlan p;
-  p.chunk = 8192;
-  while ((n + p.chunk - 1) / p.chunk > 65536) p.chunk *= 2;
+  p.chunk = kWaveRows;
+  while ((n + p.chunk - 1) / p.chunk > (1 << 20)) p.chunk *= 2;  // at most 2^20 wave tiles
   p.ntiles = (int)((n + p.chunk - 1) / p.chunk);
   return p;
 }
@@ -411,9 +409,10 @@ extern "C" int lms_hash_join(const lms_join_table* t, const lms_batch* probe, in
   if (probe->nrows == 0) {
     LMS_LAUNCH("k_jp_empty", k_jp_empty, dim3(1), dim3(64), 0, st, d_count);
   } else {
-    LMS_LAUNCH("k_jp_probe", k_jp_probe, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+    const unsigned wgs = (unsigned)((p.ntiles + kTPB / 64 - 1) / (kTPB / 64));  // one wave per tile
+    LMS_LAUNCH("k_jp_probe", k_jp_probe, dim3(wgs), dim3(kTPB), 0, st, a);
     LMS_LAUNCH("k_jp_scan", k_jp_scan, dim3(1), dim3(kScanThreads), 0, st, a);
-    LMS_LAUNCH("k_jp_write", k_jp_write, dim3(p.ntiles), dim3(kTPB), 0, st, a);
+    LMS_LAUNCH("k_jp_write", k_jp_write, dim3(wgs), dim3(kTPB), 0, st, a);
   }
   return check_hip(hipGetLastError(), "hash_join launch");
 }

@@ -676,41 +676,59 @@ __device__ int64_t reserve_output(const WinArgs& a, Lds& s, uint32_t total) {
 // Tumbling windows: every group (key, pane) is one output row.
 template <int MA>
 __device__ void emit_tumbling(const WinArgs& a, Lds& s, int64_t b0) {
+  // Wave w takes slots w * 64 + lane, then every kAggTPB further.  After one
+  // count and one reservation, each wave writes its groups at a running offset
+  // ranked by ballots -- no workgroup barrier while the stores drain.
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1;
   uint32_t mine = 0;
-  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) mine += s.gid[g] != kEmptyGid;
-  const uint32_t total = block_sum<kAggTPB>(mine, s.scan);
-  if (total == 0) return;
-  const int64_t base = reserve_output(a, s, total);
-  uint32_t run = 0;
-  for (int g0 = 0; g0 < a.eg; g0 += kAggTPB) {
-    const int g = g0 + threadIdx.x;
+  for (int g0 = (int)wave * 64; g0 < a.eg; g0 += kAggTPB) {
+    const int g = g0 + (int)lane;
+    mine += (uint32_t)__popcll(__ballot(g < a.eg && s.gid[g] != kEmptyGid));
+  }
+  if (lane == 0) s.scan[wave] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kAggTPB / 64; ++w) {
+      const uint32_t v = s.scan[w];
+      s.scan[w] = t;
+      t += v;
+    }
+    const unsigned long long b = t ? atomicAdd((unsigned long long*)&a.d_count[0], (unsigned long long)t) : 0ull;
+    s.misc[M_BASE_LO] = (uint32_t)b;
+    s.misc[M_BASE_HI] = (uint32_t)(b >> 32);
+    s.scan[kAggTPB / 64] = t;
+  }
+  __syncthreads();
+  if (s.scan[kAggTPB / 64] == 0) return;
+  int64_t run = (int64_t)(((uint64_t)s.misc[M_BASE_HI] << 32) | s.misc[M_BASE_LO]) + s.scan[wave];
+  for (int g0 = (int)wave * 64; g0 < a.eg; g0 += kAggTPB) {
+    const int g = g0 + (int)lane;
     const bool occ = g < a.eg && s.gid[g] != kEmptyGid;
-    uint32_t rtot;
-    const uint32_t r = block_excl_scan<kAggTPB>(occ ? 1u : 0u, s.scan, &rtot);
-    if (occ) {
-      const int64_t idx = base + run + r;
-      if (idx < a.cap) {
-        const uint64_t gid = s.gid[g];
-        const uint32_t cnt = s.gcnt[g];
-        a.okey[idx] = key_of(a, s, (uint32_t)(gid >> 32));
-        a.ows[idx] = a.origin + (b0 + (int64_t)(uint32_t)gid) * a.len;
-        // unrolled over the aggregate bound so each aggregate's function, slot and
-        // output pointer are compile-time kernel-argument offsets (scalar registers)
+    const uint64_t m = __ballot(occ);
+    const int64_t idx = run + __popcll(m & below);
+    run += __popcll(m);
+    if (occ && idx < a.cap) {
+      const uint64_t gid = s.gid[g];
+      const uint32_t cnt = s.gcnt[g];
+      a.okey[idx] = key_of(a, s, (uint32_t)(gid >> 32));
+      a.ows[idx] = a.origin + (b0 + (int64_t)(uint32_t)gid) * a.len;
+      // unrolled over the aggregate bound so each aggregate's function, slot and
+      // output pointer are compile-time kernel-argument offsets (scalar registers)
 #pragma unroll
-        for (int k = 0; k < kMaxAggs; ++k) {
-          if (k >= a.nagg) break;
-          const int fn = a.afn[k];
-          if (fn == LMS_COUNT) {
-            ((int64_t*)a.oagg[k])[idx] = cnt;
-          } else {
-            const uint64_t v = s.acc[(size_t)a.aacc[k] * a.eg + g];
-            if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)v) / (double)cnt;
-            else ((int64_t*)a.oagg[k])[idx] = (int64_t)v;
-          }
+      for (int k = 0; k < kMaxAggs; ++k) {
+        if (k >= a.nagg) break;
+        const int fn = a.afn[k];
+        if (fn == LMS_COUNT) {
+          ((int64_t*)a.oagg[k])[idx] = cnt;
+        } else {
+          const uint64_t v = s.acc[(size_t)a.aacc[k] * a.eg + g];
+          if (fn == LMS_AVG) ((double*)a.oagg[k])[idx] = __longlong_as_double((long long)v) / (double)cnt;
+          else ((int64_t*)a.oagg[k])[idx] = (int64_t)v;
         }
       }
     }
-    run += rtot;
   }
 }
 
@@ -1006,31 +1024,46 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg)
 // partial region [start, ...), reserving their slots with one global atomic.
 template <int MA>
 __device__ void flush_partials(const WinArgs& a, Lds& s, const Item& it) {
+  // per-wave counts, one reservation, then barrier-free ballot-ranked writes
+  // (the slot layout of emit_tumbling)
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1;
   uint32_t mine = 0;
-  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) mine += s.gid[g] != kEmptyGid;
-  const uint32_t total = block_sum<kAggTPB>(mine, s.scan);
-  if (total == 0) return;
-  if (threadIdx.x == 0) s.misc[M_PC] = a.pinfo[it.p].start + atomicAdd(&a.pfill[it.p], total);
+  for (int g0 = (int)wave * 64; g0 < a.eg; g0 += kAggTPB) {
+    const int g = g0 + (int)lane;
+    mine += (uint32_t)__popcll(__ballot(g < a.eg && s.gid[g] != kEmptyGid));
+  }
+  if (lane == 0) s.scan[wave] = mine;
   __syncthreads();
-  const uint32_t dst = s.misc[M_PC];
-  __syncthreads();
-  uint32_t run = 0;
-  for (int g0 = 0; g0 < a.eg; g0 += kAggTPB) {
-    const int g = g0 + threadIdx.x;
-    const bool occ = g < a.eg && s.gid[g] != kEmptyGid;
-    uint32_t rtot;
-    const uint32_t r = block_excl_scan<kAggTPB>(occ ? 1u : 0u, s.scan, &rtot);
-    if (occ) {
-      const uint32_t e = dst + run + r;
-      const uint64_t gid = s.gid[g];
-      a.pkey[e] = key_of(a, s, (uint32_t)(gid >> 32));
-      a.ppane[e] = (uint32_t)gid;
-      a.pcnt[e] = s.gcnt[g];
-#pragma unroll
-      for (int k = 0; k < MA; ++k)
-        if (k < a.nacc) a.pacc[k][e] = s.acc[(size_t)k * a.eg + g];
+  if (threadIdx.x == 0) {
+    uint32_t t = 0;
+    for (int w = 0; w < kAggTPB / 64; ++w) {
+      const uint32_t v = s.scan[w];
+      s.scan[w] = t;
+      t += v;
     }
-    run += rtot;
+    s.misc[M_PC] = t ? a.pinfo[it.p].start + atomicAdd(&a.pfill[it.p], t) : 0u;
+    s.scan[kAggTPB / 64] = t;
+  }
+  __syncthreads();
+  if (s.scan[kAggTPB / 64] != 0) {
+    uint32_t run = s.misc[M_PC] + s.scan[wave];
+    for (int g0 = (int)wave * 64; g0 < a.eg; g0 += kAggTPB) {
+      const int g = g0 + (int)lane;
+      const bool occ = g < a.eg && s.gid[g] != kEmptyGid;
+      const uint64_t m = __ballot(occ);
+      const uint32_t e = run + (uint32_t)__popcll(m & below);
+      run += (uint32_t)__popcll(m);
+      if (occ) {
+        const uint64_t gid = s.gid[g];
+        a.pkey[e] = key_of(a, s, (uint32_t)(gid >> 32));
+        a.ppane[e] = (uint32_t)gid;
+        a.pcnt[e] = s.gcnt[g];
+#pragma unroll
+        for (int k = 0; k < MA; ++k)
+          if (k < a.nacc) a.pacc[k][e] = s.acc[(size_t)k * a.eg + g];
+      }
+    }
   }
   __syncthreads();
 }

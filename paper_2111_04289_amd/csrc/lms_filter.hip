@@ -34,7 +34,7 @@ struct FpArgs {
 // (chunk = kWaveRows), processed in rounds of kRows sub-rounds of 64
 // consecutive rows with lane l on row b0 + u * 64 + l, so every column load of
 // a wave is one contiguous run and no workgroup-level step is needed.
-constexpr int kWaveRows = 64 * kRows * 4;
+constexpr int kWaveRows = 64 * kRows * 8;
 
 __device__ __forceinline__ int64_t wave_tile() { return ((int64_t)blockIdx.x * kTPB + threadIdx.x) >> 6; }
 

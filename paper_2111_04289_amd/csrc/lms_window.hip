@@ -34,6 +34,7 @@ namespace lms {
 namespace {
 
 constexpr int kScanTPB = 256;
+constexpr int kScatterTPB = 512;  // more waves in flight for the scatter's dependent load/atomic/store steps
 constexpr int kAggTPB = 1024;
 // Waves per SIMD the aggregation kernels are compiled for: one 1024-thread
 // workgroup per CU (what the default 2048-slot LDS tables allow) is 4 waves
@@ -357,7 +358,7 @@ __device__ __forceinline__ uint64_t staged_bits(const WinArgs& a, int v, int64_t
 // cursor atomic, so the loads overlap and rows that fail are never read.
 template <int MA>
 __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
-  for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
+  for (int p = threadIdx.x; p < a.nparts; p += kScatterTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
   __syncthreads();
   const int64_t b0 = a.hdr[0];
   const int64_t lo = (int64_t)w * a.chunk;
@@ -367,13 +368,13 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
   const void* tc = a.q.col[a.ts_col];
   const int tdt = a.q.dt[a.ts_col];
   bool range_err = false;
-  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kUnroll) {
+  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScatterTPB * kUnroll) {
     bool ok[kUnroll];
     int64_t key[kUnroll], ts[kUnroll], idx[kUnroll];
     uint64_t val[kUnroll][MA];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      idx[u] = b + (int64_t)u * kScanTPB;
+      idx[u] = b + (int64_t)u * kScatterTPB;
       ok[u] = idx[u] < hi;
     }
     rows_pass<kUnroll>(a.q, idx, ok);
@@ -413,7 +414,7 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
 }
 
 template <int MA>
-__global__ __launch_bounds__(kScanTPB) void k_wa_scatter(WinArgs a) {
+__global__ __launch_bounds__(kScatterTPB) void k_wa_scatter(WinArgs a) {
   extern __shared__ uint32_t cursor[];
   if constexpr (MA == 8) {
     // at this unroll bound the loops over value columns stay rolled and would
@@ -1302,7 +1303,7 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scan2(const char* desc, MultiL
 }
 
 template <int MA>
-__global__ __launch_bounds__(kScanTPB) void k_wam_scatter(const char* desc, MultiLim lim) {
+__global__ __launch_bounds__(kScatterTPB) void k_wam_scatter(const char* desc, MultiLim lim) {
   extern __shared__ uint32_t cursor[];
   __shared__ WinArgs sa;
   const MultiView v = multi_view(desc);
@@ -1550,7 +1551,7 @@ void launch_tail(const Plan& p, const WinArgs& a, size_t plds, hipStream_t st) {
   // workgroups as the CUs hold at once: one per CU (a 1024-thread workgroup
   // already fills each SIMD's register budget at 4 waves)
   const int resident = num_cus();
-  LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);
+  LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScatterTPB), plds, st, a);
   LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(std::min(p.max_items, resident)), dim3(kAggTPB), p.lds, st, a);
   LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(std::min(p.nparts, resident)), dim3(kAggTPB), p.lds, st, a);
 }
@@ -1674,7 +1675,7 @@ int launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
   LMS_LAUNCH("k_wam_scan1", k_wam_scan1, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scanp", k_wam_scanp, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scan2", k_wam_scan2, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
-  LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
+  LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScatterTPB), plds, st, desc, lim);
   LMS_LAUNCH("k_wam_agg", k_wam_agg<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
   LMS_LAUNCH("k_wam_merge", k_wam_merge<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
   return LMS_OK;

@@ -142,7 +142,7 @@ __device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)
 // processed in rounds of kProbe sub-rounds of 64 consecutive rows with lane l
 // on row b0 + u * 64 + l, so key loads and record stores are contiguous per
 // wave, and no step needs a workgroup barrier.
-constexpr int kWaveRows = 64 * kProbe * 16;
+constexpr int kWaveRows = 64 * kProbe * 8;
 
 __device__ __forceinline__ int64_t wave_tile() { return ((int64_t)blockIdx.x * kTPB + threadIdx.x) >> 6; }
 

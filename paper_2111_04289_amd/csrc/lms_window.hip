@@ -34,7 +34,7 @@ namespace lms {
 namespace {
 
 constexpr int kScanTPB = 256;
-constexpr int kScatterTPB = 512;  // more waves in flight for the scatter's dependent load/atomic/store steps
+constexpr int kScatterTPB = 256;  // measured: 512 threads per chunk ran slower
 constexpr int kAggTPB = 1024;
 // Waves per SIMD the aggregation kernels are compiled for: one 1024-thread
 // workgroup per CU (what the default 2048-slot LDS tables allow) is 4 waves

@@ -899,15 +899,30 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   }
   __syncthreads();
   if (total == 0) return;
-  const int64_t base = reserve_output(a, s, total);
+  // The group ids are dead from here on, so their slots hold a row -> entry
+  // map (16-bit entries, 4 per id slot) whenever the rows fit; each entry
+  // fills in the rows of the windows it owns.
+  uint16_t* const rmap = (uint16_t*)s.gid;
+  const bool mapped = total <= 4u * (uint32_t)a.eg && ng <= 65536u;
+  if (mapped) {
+    for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
+      const uint32_t end = i + 1 < ng ? s.order[i + 1] : total;
+      for (uint32_t r = s.order[i]; r < end; ++r) rmap[r] = (uint16_t)i;
+    }
+  }
+  const int64_t base = reserve_output(a, s, total);  // its barrier publishes the map
   const int64_t wbase = b0 / a.R;
   // Rows go out in blocks of 64, one per lane, each wave taking every
-  // (kAggTPB / 64)-th block.  Lane 0 finds the block's first entry and
-  // broadcasts it; every lane then searches only the block's entries (at most
-  // 64 R of them, as each owned window spans at most R panes).  Nothing here
-  // needs a workgroup barrier, so a wave's output stores overlap its next
-  // block instead of being waited for.
+  // (kAggTPB / 64)-th block.  Nothing here needs a workgroup barrier, so a
+  // wave's output stores overlap its next block instead of being waited for.
   const uint32_t lane = threadIdx.x & 63;
+  if (mapped) {
+    for (uint32_t r = threadIdx.x; r < total; r += kAggTPB) emit_row<MA>(a, s, rmap[r], r, base, wbase);
+    return;
+  }
+  // Without the map, lane 0 finds the block's first entry and broadcasts it;
+  // every lane then searches only the block's entries (at most 64 R of them,
+  // as each owned window spans at most R panes).
   const uint32_t span = (uint32_t)min<int64_t>(64 * a.R, ng);
   for (uint32_t r0 = (threadIdx.x >> 6) * 64; r0 < total; r0 += kAggTPB) {
     uint32_t i0 = 0;

@@ -188,29 +188,54 @@ __device__ __forceinline__ uint32_t block_scan_array(uint32_t* arr, int n, uint3
 }
 
 // Single-workgroup exclusive scan of n int64 tile counts (TPB threads, each
-// scanning a contiguous run); writes off[0..n) and *total.
+// scanning a contiguous run); writes off[0..n) and, from thread 0, *total.
+// The per-thread sums are scanned with wave shuffles and one wave over the
+// wave totals, so no thread walks all TPB sums.
 template <int TPB>
 __device__ void tile_offsets(const int64_t* cnt, int64_t* off, int n, int64_t* total) {
-  __shared__ int64_t sums[TPB];
+  static_assert(TPB % 64 == 0 && TPB / 64 <= 64, "one wave scans the wave totals");
+  __shared__ int64_t wsum[TPB / 64 + 1];
   const int per = (n + TPB - 1) / TPB;
   const int lo = threadIdx.x * per;
   const int hi = min(n, lo + per);
+  constexpr int kHeld = 8;  // the first counts of the run are loaded together and kept
+  int64_t held[kHeld];
   int64_t s = 0;
-  for (int i = lo; i < hi; ++i) s += cnt[i];
-  sums[threadIdx.x] = s;
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j) {
+    held[j] = lo + j < hi ? cnt[lo + j] : 0;
+    s += held[j];
+  }
+  for (int i = lo + kHeld; i < hi; ++i) s += cnt[i];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = s;  // inclusive scan over the wave
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int t = 0; t < TPB; ++t) {
-      const int64_t v = sums[t];
-      sums[t] = run;
-      run += v;
+  if (wave == 0) {
+    const int64_t v = lane < TPB / 64 ? wsum[lane] : 0;
+    int64_t y = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t z = __shfl_up(y, d, 64);
+      if (lane >= d) y += z;
     }
-    *total = run;
+    if (lane < TPB / 64) wsum[lane] = y - v;
+    if (lane == TPB / 64 - 1) wsum[TPB / 64] = y;
   }
   __syncthreads();
-  int64_t run = sums[threadIdx.x];
-  for (int i = lo; i < hi; ++i) {
+  if (threadIdx.x == 0) *total = wsum[TPB / 64];
+  int64_t run = wsum[wave] + x - s;
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j) {
+    if (lo + j < hi) off[lo + j] = run;
+    run += held[j];
+  }
+  for (int i = lo + kHeld; i < hi; ++i) {
     const int64_t v = cnt[i];
     off[i] = run;
     run += v;

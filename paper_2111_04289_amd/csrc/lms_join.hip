@@ -6,13 +6,15 @@
 // with one 32-bit CAS, duplicate keys take separate slots.  All slots of a key
 // lie in the run of used slots that starts at its home slot, so a probe walks
 // from the home slot to the first unused slot.
-// Probe: one pass walks the chains and records each row's match count and
-// first payload (8 bytes per row, coalesced) with per-tile totals (a tile is
+// Probe: one pass walks the chains (a row's walk stops at its match when the
+// build found no repeated key) and records each row's match count and first
+// payload (8 bytes per row, coalesced) with per-tile totals (a tile is
 // one wave's contiguous range); a scan of the tile counts; then a write pass
 // that ranks rows with a wave scan and a running offset, so the pairs come out
 // grouped by ascending probe row without global atomics or workgroup
-// barriers, and touches the table again only for rows with several matches.  Each thread walks the chains of several consecutive rows in
-// lockstep to overlap the random slot reads (the table is MALL-resident, not
+// barriers, and touches the table again only for rows with several matches.
+// Each thread walks the chains of several consecutive rows in lockstep to
+// overlap the random slot reads (the table is MALL-resident, not
 // L2-resident).
 #include <algorithm>
 
@@ -102,14 +104,16 @@ struct ProbeArgs {
   int32_t* out_pay;
   int64_t cap;
   int64_t* d_count;
+  const int64_t* d_mult;  // largest number of build rows sharing one key
 };
 
 // Walks the probe chains of kProbe consecutive rows in lockstep, so their slot
 // loads are independent; calls hit(u, payload) for every match of row u, in
-// chain order.
+// chain order.  With first_only (no key occurs twice in the table) a row's
+// walk ends at its match instead of at the end of the run.
 template <class F>
 __device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)[kProbe], const bool (&valid)[kProbe],
-                                          F hit) {
+                                          bool first_only, F hit) {
   uint64_t s[kProbe];
   bool active[kProbe];
 #pragma unroll
@@ -130,7 +134,13 @@ __device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)
         active[u] = false;
         continue;
       }
-      if (sl[u].key == k[u]) hit(u, sl[u].pay);
+      if (sl[u].key == k[u]) {
+        hit(u, sl[u].pay);
+        if (first_only) {
+          active[u] = false;
+          continue;
+        }
+      }
       s[u] = (s[u] + 1) & a.mask;
       any = true;
     }
@@ -169,6 +179,7 @@ __global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
   const int64_t lo = t * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
   const int lane = threadIdx.x & 63;
+  const bool first_only = *a.d_mult <= 1;
   uint32_t c = 0;
   for (int64_t b0 = lo; b0 < hi; b0 += 64 * kProbe) {
     int64_t k[kProbe], idx[kProbe];
@@ -183,7 +194,7 @@ __global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
       cnt[u] = 0;
       first[u] = 0;
     }
-    walk_rows(a, k, valid, [&](int u, int32_t pay) {
+    walk_rows(a, k, valid, first_only, [&](int u, int32_t pay) {
       if (cnt[u] == 0) first[u] = (uint32_t)pay;
       ++cnt[u];
     });
@@ -410,6 +421,7 @@ extern "C" int lms_hash_join(const lms_join_table* t, const lms_batch* probe, in
   a.out_pay = out_payload;
   a.cap = cap;
   a.d_count = d_count;
+  a.d_mult = t->d_mult;
   hipStream_t st = (hipStream_t)stream;
   // the build may run on another stream: order this probe after it
   int rc = check_hip(hipStreamWaitEvent(st, t->built, 0), "hipStreamWaitEvent");

@@ -215,6 +215,7 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan1(WinArgs a) {
 }
 
 constexpr int kMaxParts = 4096;  // partitions of one batch (make_plan's bound)
+constexpr int kPlanTPB = 1024;   // threads of the planning workgroup: a few partitions each
 
 // Partition starts and the aggregation work items of one batch (one
 // workgroup; r, st, kc, base are kMaxParts-word LDS arrays):
@@ -231,14 +232,14 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
                            uint32_t* scratch) {
   const int np = a.nparts;
   const uint32_t rs = (uint32_t)a.rs, pack = (uint32_t)a.eg / 4;
-  for (int p = threadIdx.x; p < np; p += kScanTPB) {
+  for (int p = threadIdx.x; p < np; p += kPlanTPB) {
     const uint32_t v = a.Rp[p];
     r[p] = v;
     st[p] = v;
   }
   __syncthreads();
-  const uint32_t total = block_scan_array<kScanTPB>(st, np, scratch);
-  for (int p = threadIdx.x; p < np; p += kScanTPB) {
+  const uint32_t total = block_scan_array<kPlanTPB>(st, np, scratch);
+  for (int p = threadIdx.x; p < np; p += kPlanTPB) {
     const uint32_t v = r[p];
     uint32_t k = 0;
     if (v > rs) {
@@ -260,8 +261,8 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
     base[p] = k;
   }
   __syncthreads();
-  const uint32_t nitems = block_scan_array<kScanTPB>(base, np, scratch);
-  for (int p = threadIdx.x; p < np; p += kScanTPB) {
+  const uint32_t nitems = block_scan_array<kPlanTPB>(base, np, scratch);
+  for (int p = threadIdx.x; p < np; p += kPlanTPB) {
     const uint32_t v = r[p], k = kc[p], ib = base[p], s0 = st[p];
     if (k > 0) {
       Item it;
@@ -297,10 +298,10 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
   }
   __syncthreads();
   // list of the split partitions (the merge pass claims them one by one)
-  for (int p = threadIdx.x; p < np; p += kScanTPB) kc[p] = r[p] > rs ? 1u : 0u;
+  for (int p = threadIdx.x; p < np; p += kPlanTPB) kc[p] = r[p] > rs ? 1u : 0u;
   __syncthreads();
-  const uint32_t nsplit = block_scan_array<kScanTPB>(kc, np, scratch);
-  for (int p = threadIdx.x; p < np; p += kScanTPB)
+  const uint32_t nsplit = block_scan_array<kPlanTPB>(kc, np, scratch);
+  for (int p = threadIdx.x; p < np; p += kPlanTPB)
     if (r[p] > rs) a.splits[kc[p]] = (uint32_t)p;
   if (threadIdx.x == 0) {
     a.hdr[1] = nitems;
@@ -309,9 +310,9 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kScanTPB) void k_wa_scanp(WinArgs a) {
+__global__ __launch_bounds__(kPlanTPB) void k_wa_scanp(WinArgs a) {
   __shared__ uint32_t r[kMaxParts], st[kMaxParts], kc[kMaxParts], base[kMaxParts];
-  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  __shared__ uint32_t scratch[kPlanTPB / 64 + 1];
   plan_items(a, r, st, kc, base, scratch);
 }
 
@@ -1291,9 +1292,9 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scan1(const char* desc, MultiL
   }
 }
 
-__global__ __launch_bounds__(kScanTPB) void k_wam_scanp(const char* desc, MultiLim lim) {
+__global__ __launch_bounds__(kPlanTPB) void k_wam_scanp(const char* desc, MultiLim lim) {
   __shared__ uint32_t r[kMaxParts], st[kMaxParts], kc[kMaxParts], base[kMaxParts];
-  __shared__ uint32_t scratch[kScanTPB / 64 + 1];
+  __shared__ uint32_t scratch[kPlanTPB / 64 + 1];
   __shared__ WinArgs sa;
   const MultiView v = multi_view(desc);
   if (!multi_fits(v.hdr, lim)) return;
@@ -1688,7 +1689,7 @@ int launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
   LMS_LAUNCH("k_wam_init", k_wam_init, dim3(4), dim3(256), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_hist", k_wam_hist, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
   LMS_LAUNCH("k_wam_scan1", k_wam_scan1, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
-  LMS_LAUNCH("k_wam_scanp", k_wam_scanp, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
+  LMS_LAUNCH("k_wam_scanp", k_wam_scanp, dim3(c.grid_scan), dim3(kPlanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scan2", k_wam_scan2, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScatterTPB), plds, st, desc, lim);
   LMS_LAUNCH("k_wam_agg", k_wam_agg<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
@@ -1713,7 +1714,7 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
     const size_t plds = (size_t)p.nparts * 4;
     LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);
     LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
-    LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kScanTPB), 0, st, a);
+    LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kPlanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
     // loops over accumulators are unrolled to the smallest bound covering them
     const int ma = acc_bound(a.nacc);

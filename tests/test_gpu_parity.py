@@ -64,6 +64,47 @@ def test_filter_project_parity(lms, n, seed):
             np.testing.assert_array_equal(g, exp[j])
 
 
+def _check_filter(lms, cols, dcols, preds, keep, projs):
+    out, d = lms.lms_filter_project(dcols, preds, keep, projs)
+    torch.cuda.synchronize()
+    m, status = [int(x) for x in d.cpu()]
+    assert status == 0
+    exp = oracle.filter_project(cols, preds, keep, projs)
+    assert m == len(exp[0])
+    for j in range(len(exp)):
+        g = out[j][:m].cpu().numpy()
+        if g.dtype.kind == "f":
+            np.testing.assert_array_equal(np.isnan(g), np.isnan(exp[j]))
+            np.testing.assert_array_equal(g[~np.isnan(g)], exp[j][~np.isnan(exp[j])])
+        else:
+            np.testing.assert_array_equal(g, exp[j])
+    return m
+
+
+@pytest.mark.parametrize("n,offset", [(70001, 1), (70001, 2), (300000, 3)])
+def test_filter_project_unaligned_columns(lms, n, offset):
+    """Columns that do not start on a 16-byte boundary (views one or more rows
+    into a buffer) take the row-by-row loads; results must not change."""
+    log(f"filter_project unaligned n={n} offset={offset}")
+    full = rand_cols(11, n + offset, 50, 1000, neg=True)
+    cols = [c[offset:] for c in full]
+    dcols = [c[offset:] for c in to_dev(full)]
+    assert any(c.data_ptr() % 16 for c in dcols)
+    _check_filter(lms, cols, dcols, [(2, LT, 300), (3, NE, 0, 0.5)], [0, 1, 3], [(2, 2, 0), (0, -3, 11)])
+
+
+def test_filter_project_sparse_and_dense_tiles(lms):
+    """A predicate on the sorted time column passes every row of some tiles, a
+    few rows of others and none of the rest: dense tiles use the quad loads,
+    sparse ones the passing rows' loads, in one launch."""
+    n = 200003
+    cols = rand_cols(12, n, 50, 1000, neg=True)
+    cols[0] = np.sort(cols[0])
+    cols[0][n // 2:n // 2 + 9000:97] = -2000  # scattered passing rows in the upper half
+    m = _check_filter(lms, cols, to_dev(cols), [(0, LT, -500)], [0, 1, 2, 3], [(1, 7, -1)])
+    assert 0 < m < n
+
+
 def test_filter_project_all_and_none(lms):
     cols = rand_cols(9, 10000, 10, 100)
     for preds, expect in [([], 10000), ([(2, GE, 5000)], 0), ([(2, LE, 5000)], 10000)]:

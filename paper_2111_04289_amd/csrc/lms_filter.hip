@@ -56,23 +56,43 @@ constexpr int kQuadSteps = 4;  // quads per step: their loads are in flight toge
 constexpr int kStepRows = kQuadRows * kQuadSteps;
 static_assert(kWaveRows % kStepRows == 0, "wave tiles hold whole steps");
 
-// Raw 64-bit bits of rows r .. r + 3 (r a multiple of 4, column 16-byte aligned).
-__device__ __forceinline__ void load_quad(const void* col, int dt, int64_t r, uint64_t (&v)[4]) {
-  if (dt == LMS_I32 || dt == LMS_F32) {
-    const uint4 x = *(const uint4*)((const uint32_t*)col + r);
-    v[0] = x.x;
-    v[1] = x.y;
-    v[2] = x.z;
-    v[3] = x.w;
+// Raw 64-bit bits of the quads of a step (rows b0 + u * kQuadRows + 4 * lane
+// + e; column 16-byte aligned).  The column width is a template parameter, so
+// that a caller branches on it once around the loads and their uses: a branch
+// joining between the loads and their first use would make the wave wait for
+// each load before issuing the next.
+template <bool kWide>
+__device__ __forceinline__ void load_quads(const void* col, int64_t b0, int lane, uint64_t (&v)[kQuadSteps][4]) {
+  if constexpr (kWide) {
+    ulonglong2 x[kQuadSteps], y[kQuadSteps];
+#pragma unroll
+    for (int u = 0; u < kQuadSteps; ++u) {
+      const uint64_t* q = (const uint64_t*)col + b0 + u * kQuadRows + 4 * lane;
+      x[u] = *(const ulonglong2*)q;
+      y[u] = *(const ulonglong2*)(q + 2);
+    }
+#pragma unroll
+    for (int u = 0; u < kQuadSteps; ++u) {
+      v[u][0] = x[u].x;
+      v[u][1] = x[u].y;
+      v[u][2] = y[u].x;
+      v[u][3] = y[u].y;
+    }
   } else {
-    const ulonglong2 x = *(const ulonglong2*)((const uint64_t*)col + r);
-    const ulonglong2 y = *(const ulonglong2*)((const uint64_t*)col + r + 2);
-    v[0] = x.x;
-    v[1] = x.y;
-    v[2] = y.x;
-    v[3] = y.y;
+    uint4 x[kQuadSteps];
+#pragma unroll
+    for (int u = 0; u < kQuadSteps; ++u) x[u] = *(const uint4*)((const uint32_t*)col + b0 + u * kQuadRows + 4 * lane);
+#pragma unroll
+    for (int u = 0; u < kQuadSteps; ++u) {
+      v[u][0] = x[u].x;
+      v[u][1] = x[u].y;
+      v[u][2] = x[u].z;
+      v[u][3] = x[u].w;
+    }
   }
 }
+
+__device__ __forceinline__ bool wide_dtype(int dt) { return dt == LMS_I64 || dt == LMS_F64; }
 
 // One predicate on a value's raw bits (the comparisons of rows_pass).
 __device__ __forceinline__ bool pred_bits(uint64_t b, int dt, int op, int64_t iv, double fv) {
@@ -84,24 +104,28 @@ __device__ __forceinline__ bool pred_bits(uint64_t b, int dt, int op, int64_t iv
   }
 }
 
-// Pass masks (bit s: row b0 + u * kQuadRows + 4 * lane + s) of a step's quads;
-// every predicate's loads for all quads are issued before its comparisons.
+template <bool kWide>
+__device__ __forceinline__ void pred_quads(const Query& q, int k, int64_t b0, int lane, uint32_t (&m)[kQuadSteps]) {
+  const int c = q.pcol[k];
+  const int dt = q.dt[c], op = q.pop[k];
+  const int64_t iv = q.pival[k];
+  const double fv = q.pfval[k];
+  uint64_t v[kQuadSteps][4];
+  load_quads<kWide>(q.col[c], b0, lane, v);
+#pragma unroll
+  for (int u = 0; u < kQuadSteps; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (!pred_bits(v[u][e], dt, op, iv, fv)) m[u] &= ~(1u << e);
+}
+
+// Pass masks (bit e: row b0 + u * kQuadRows + 4 * lane + e) of a step's quads.
 __device__ __forceinline__ void quads_pass(const Query& q, int64_t b0, int lane, uint32_t (&m)[kQuadSteps]) {
 #pragma unroll
   for (int u = 0; u < kQuadSteps; ++u) m[u] = 0xF;
   for (int k = 0; k < q.npred; ++k) {
-    const int c = q.pcol[k];
-    const int dt = q.dt[c], op = q.pop[k];
-    const int64_t iv = q.pival[k];
-    const double fv = q.pfval[k];
-    uint64_t v[kQuadSteps][4];
-#pragma unroll
-    for (int u = 0; u < kQuadSteps; ++u) load_quad(q.col[c], dt, b0 + u * kQuadRows + 4 * lane, v[u]);
-#pragma unroll
-    for (int u = 0; u < kQuadSteps; ++u)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (!pred_bits(v[u][e], dt, op, iv, fv)) m[u] &= ~(1u << e);
+    if (wide_dtype(q.dt[q.pcol[k]])) pred_quads<true>(q, k, b0, lane, m);
+    else pred_quads<false>(q, k, b0, lane, m);
   }
 }
 
@@ -163,22 +187,37 @@ __device__ __forceinline__ void put_bits(void* col, int dt, int64_t r, uint64_t 
   else ((uint64_t*)col)[r] = v;
 }
 
-// Output column j of rows r .. r + 3 (quad path), as out_bits gives them.
-__device__ __forceinline__ void out_quad(const FpArgs& a, int j, int64_t r, uint64_t (&v)[4]) {
-  if (j < a.nkeep) {
-    const int c = a.keep[j];
-    load_quad(a.q.col[c], a.q.dt[c], r, v);
-    return;
-  }
+// Quad path of output column j: loads the step's quads of its source column
+// (a kept column, or a projection's source with the projection applied, as
+// out_bits gives them) and writes the passing rows from output row r[u] on.
+template <bool kWide>
+__device__ __forceinline__ void write_quads(const FpArgs& a, int j, int64_t b0, int lane,
+                                            const uint32_t (&m)[kQuadSteps], const int64_t (&r)[kQuadSteps]) {
+  const bool kept = j < a.nkeep;
   const int p = j - a.nkeep;
-  const int sc = a.q.prsrc[p];
+  const int sc = kept ? a.keep[j] : a.q.prsrc[p];
   const int dt = a.q.dt[sc];
-  load_quad(a.q.col[sc], dt, r, v);
+  uint64_t v[kQuadSteps][4];
+  load_quads<kWide>(a.q.col[sc], b0, lane, v);
+  if (!kept) {
+    const uint64_t mul = (uint64_t)a.q.prmul[p], add = (uint64_t)a.q.pradd[p];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t x = dt == LMS_I32 ? (int64_t)(int32_t)(uint32_t)v[e] : (int64_t)v[e];
-    const uint64_t raw = (uint64_t)x * (uint64_t)a.q.prmul[p] + (uint64_t)a.q.pradd[p];
-    v[e] = dt == LMS_I32 ? (uint64_t)(int64_t)(int32_t)(uint32_t)raw : raw;
+    for (int u = 0; u < kQuadSteps; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t x = dt == LMS_I32 ? (int64_t)(int32_t)(uint32_t)v[u][e] : (int64_t)v[u][e];
+        const uint64_t raw = (uint64_t)x * mul + add;
+        v[u][e] = dt == LMS_I32 ? (uint64_t)(int64_t)(int32_t)(uint32_t)raw : raw;
+      }
+  }
+  void* const out = a.out[j];
+  const int odt = a.odt[j];
+#pragma unroll
+  for (int u = 0; u < kQuadSteps; ++u) {
+    int64_t o = r[u];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if ((m[u] >> e) & 1u) put_bits(out, odt, o++, v[u][e]);
   }
 }
 
@@ -221,16 +260,9 @@ __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
         run += tot;
       }
       for (int j = 0; j < ncol; ++j) {
-        uint64_t v[kQuadSteps][4];
-#pragma unroll
-        for (int u = 0; u < kQuadSteps; ++u) out_quad(a, j, b0 + u * kQuadRows + 4 * lane, v[u]);
-#pragma unroll
-        for (int u = 0; u < kQuadSteps; ++u) {
-          int64_t o = r[u];
-#pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if ((m[u] >> e) & 1u) put_bits(a.out[j], a.odt[j], o++, v[u][e]);
-        }
+        const int sc = j < a.nkeep ? a.keep[j] : a.q.prsrc[j - a.nkeep];
+        if (wide_dtype(a.q.dt[sc])) write_quads<true>(a, j, b0, lane, m, r);
+        else write_quads<false>(a, j, b0, lane, m, r);
       }
     }
   }

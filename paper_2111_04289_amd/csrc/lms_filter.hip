@@ -154,7 +154,7 @@ __global__ __launch_bounds__(kTPB) void k_fp_count(FpArgs a) {
       idx[u] = b0 + (int64_t)u * 64 + lane;
       ok[u] = idx[u] < hi;
     }
-    rows_pass<kRows>(a.q, idx, ok);
+    rows_pass<kRows>(a.q, idx, ok, lo);
 #pragma unroll
     for (int u = 0; u < kRows; ++u) c += (uint32_t)__popcll(__ballot(ok[u]));
   }
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
       idx[u] = b0 + (int64_t)u * 64 + lane;
       pass[u] = idx[u] < hi;
     }
-    rows_pass<kRows>(a.q, idx, pass);
+    rows_pass<kRows>(a.q, idx, pass, lo);
     int64_t r[kRows];
 #pragma unroll
     for (int u = 0; u < kRows; ++u) {

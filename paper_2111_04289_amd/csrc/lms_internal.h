@@ -71,24 +71,76 @@ __device__ __forceinline__ bool row_passes(const Query& q, int64_t i) {
   return ok;
 }
 
+// Rows idx[u] (where ld[u]; 0 elsewhere) of a column, U at a time.  Every
+// lane issues all U loads unconditionally, a row that is not needed reading
+// row `safe` (any valid row: the same line for all of them) instead, and only
+// then converts: a load under a per-row branch gets its conversion or
+// comparison moved into the branch, which makes the wave wait for each load
+// before issuing the next one.
+template <int U>
+__device__ __forceinline__ void load_i64_rows(const void* p, int dt, const int64_t (&idx)[U], const bool (&ld)[U],
+                                              int64_t safe, int64_t (&v)[U]) {
+  if (dt == LMS_I32) {
+    int32_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = ((const int32_t*)p)[ld[u] ? idx[u] : safe];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = ld[u] ? (int64_t)x[u] : 0;
+  } else {
+    int64_t x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = ((const int64_t*)p)[ld[u] ? idx[u] : safe];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = ld[u] ? x[u] : 0;
+  }
+}
+
+template <int U>
+__device__ __forceinline__ void load_f64_rows(const void* p, int dt, const int64_t (&idx)[U], const bool (&ld)[U],
+                                              int64_t safe, double (&v)[U]) {
+  switch (dt) {
+    case LMS_F32: {
+      float x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ((const float*)p)[ld[u] ? idx[u] : safe];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = ld[u] ? (double)x[u] : 0.0;
+      break;
+    }
+    case LMS_F64: {
+      double x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ((const double*)p)[ld[u] ? idx[u] : safe];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = ld[u] ? x[u] : 0.0;
+      break;
+    }
+    default: {
+      int64_t x[U];
+      load_i64_rows<U>(p, dt, idx, ld, safe, x);
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = (double)x[u];
+    }
+  }
+}
+
 // Predicates of U rows at once (rows idx[u] with valid[u]): for each predicate
 // the U loads are issued together, so the rows' memory latencies overlap.
+// Rows outside the range (ok[u] false on entry) read row `safe` (any valid row).
 template <int U>
-__device__ __forceinline__ void rows_pass(const Query& q, const int64_t (&idx)[U], bool (&ok)[U]) {
+__device__ __forceinline__ void rows_pass(const Query& q, const int64_t (&idx)[U], bool (&ok)[U], int64_t safe) {
   for (int k = 0; k < q.npred; ++k) {
     const int c = q.pcol[k];
     const int dt = q.dt[c];
     const void* col = q.col[c];
     if (is_int_dtype(dt)) {
       int64_t v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = ok[u] ? load_i64(col, dt, idx[u]) : 0;
+      load_i64_rows<U>(col, dt, idx, ok, safe, v);
 #pragma unroll
       for (int u = 0; u < U; ++u) ok[u] = ok[u] && compare<int64_t>(v[u], q.pop[k], q.pival[k]);
     } else {
       double v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = ok[u] ? load_f64(col, dt, idx[u]) : 0.0;
+      load_f64_rows<U>(col, dt, idx, ok, safe, v);
 #pragma unroll
       for (int u = 0; u < U; ++u) ok[u] = ok[u] && compare<double>(v[u], q.pop[k], q.pfval[k]);
     }
@@ -111,6 +163,24 @@ __device__ __forceinline__ int64_t ext_i64(const Query& q, int c, int64_t i) {
 }
 __device__ __forceinline__ double ext_f64(const Query& q, int c, int64_t i) {
   return c < q.ncols ? load_f64(q.col[c], q.dt[c], i) : (double)project(q, c - q.ncols, i);
+}
+
+// ext_i64 of rows idx[u] (where ld[u]), U at a time (see load_i64_rows).
+template <int U>
+__device__ __forceinline__ void ext_i64_rows(const Query& q, int c, const int64_t (&idx)[U], const bool (&ld)[U],
+                                             int64_t safe, int64_t (&v)[U]) {
+  if (c < q.ncols) {
+    load_i64_rows<U>(q.col[c], q.dt[c], idx, ld, safe, v);
+    return;
+  }
+  const int j = c - q.ncols;
+  const int s = q.prsrc[j];
+  load_i64_rows<U>(q.col[s], q.dt[s], idx, ld, safe, v);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const uint64_t raw = (uint64_t)v[u] * (uint64_t)q.prmul[j] + (uint64_t)q.pradd[j];
+    v[u] = q.dt[s] == LMS_I32 ? (int64_t)(int32_t)(uint32_t)raw : (int64_t)raw;
+  }
 }
 
 // MurmurHash3 64-bit finaliser (Appleby), a bijective avalanche mixer.

@@ -182,9 +182,8 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
       idx[u] = b + (int64_t)u * kScanTPB;
       ok[u] = idx[u] < hi;
     }
-    rows_pass<kHistUnroll>(a.q, idx, ok);
-#pragma unroll
-    for (int u = 0; u < kHistUnroll; ++u) key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
+    rows_pass<kHistUnroll>(a.q, idx, ok, lo);
+    load_i64_rows<kHistUnroll>(kc, kdt, idx, ok, lo, key);
 #pragma unroll
     for (int u = 0; u < kHistUnroll; ++u)
       if (ok[u]) atomicAdd(&hist[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
@@ -342,21 +341,44 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
   scan2_part(a, blockIdx.x, scratch);
 }
 
-// Raw bits of staged value column v at row i (int64, or the float's own bits).
-__device__ __forceinline__ uint64_t staged_bits(const WinArgs& a, int v, int64_t i) {
+// Raw bits of staged value column v (int64, or the float's own bits) for rows
+// idx[u] where ld[u], U at a time (see load_i64_rows).
+template <int U>
+__device__ __forceinline__ void staged_rows(const WinArgs& a, int v, const int64_t (&idx)[U], const bool (&ld)[U],
+                                            int64_t safe, uint64_t (&x)[U]) {
   const int c = a.vcol[v];
   switch (a.vdt[v]) {
     case LMS_I32:
-    case LMS_I64: return (uint64_t)ext_i64(a.q, c, i);
-    case LMS_F32: return (uint64_t)__float_as_uint(((const float*)a.q.col[c])[i]);
-    default: return ((const uint64_t*)a.q.col[c])[i];
+    case LMS_I64: {
+      int64_t y[U];
+      ext_i64_rows<U>(a.q, c, idx, ld, safe, y);
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = (uint64_t)y[u];
+      break;
+    }
+    case LMS_F32: {
+      uint32_t y[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) y[u] = ((const uint32_t*)a.q.col[c])[ld[u] ? idx[u] : safe];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ld[u] ? y[u] : 0u;
+      break;
+    }
+    default: {
+      uint64_t y[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) y[u] = ((const uint64_t*)a.q.col[c])[ld[u] ? idx[u] : safe];
+#pragma unroll
+      for (int u = 0; u < U; ++u) x[u] = ld[u] ? y[u] : 0;
+    }
   }
 }
 
 // Scatter the passing rows, as (key, pane, value columns), to their partition.
 // The predicate columns are read first; every other column a passing row
 // needs is then loaded for all kUnroll rows of a thread before the first LDS
-// cursor atomic, so the loads overlap and rows that fail are never read.
+// cursor atomic, so the loads overlap, and rows that fail read one shared row
+// in their place, so a selective predicate leaves most lines unread.
 template <int MA>
 __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
   for (int p = threadIdx.x; p < a.nparts; p += kScatterTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
@@ -378,13 +400,20 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
       idx[u] = b + (int64_t)u * kScatterTPB;
       ok[u] = idx[u] < hi;
     }
-    rows_pass<kUnroll>(a.q, idx, ok);
+    rows_pass<kUnroll>(a.q, idx, ok, lo);
+    load_i64_rows<kUnroll>(kc, kdt, idx, ok, lo, key);
+    load_i64_rows<kUnroll>(tc, tdt, idx, ok, lo, ts);
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      key[u] = ok[u] ? load_i64(kc, kdt, idx[u]) : 0;
-      ts[u] = ok[u] ? load_i64(tc, tdt, idx[u]) : 0;
+    for (int v = 0; v < MA; ++v) {
+      if (v < a.nval) {
+        uint64_t x[kUnroll];
+        staged_rows<kUnroll>(a, v, idx, ok, lo, x);
 #pragma unroll
-      for (int v = 0; v < MA; ++v) val[u][v] = (ok[u] && v < a.nval) ? staged_bits(a, v, idx[u]) : 0;
+        for (int u = 0; u < kUnroll; ++u) val[u][v] = x[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) val[u][v] = 0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {

@@ -250,23 +250,33 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # timed region: step events plus per-kernel events recorded by the library
+    # timed region: K steps between two events, nothing else on the stream
     stream = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     begin, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    if not args.no_trace:
-        lms.lms_trace_enable(True)
     torch.cuda.synchronize()
     begin.record(stream)
+    for k in range(args.steps):
+        step()
+    end.record(stream)
+    torch.cuda.synchronize()
+    total_ms = begin.elapsed_time(end)
+    # per-step spread (p50/p99) from a second pass of K steps with an event
+    # pair around each, and per-kernel durations from a third with the
+    # library's per-kernel events
     for k in range(args.steps):
         evs[k][0].record(stream)
         step()
         evs[k][1].record(stream)
-    end.record(stream)
     torch.cuda.synchronize()
-    lms.lms_trace_enable(False)
-    trace = lms.lms_trace_read() if not args.no_trace else {}
-    total_ms = begin.elapsed_time(end)
+    trace = {}
+    if not args.no_trace:
+        lms.lms_trace_enable(True)
+        for k in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        lms.lms_trace_enable(False)
+        trace = lms.lms_trace_read()
     step_ms = np.array([a.elapsed_time(b) for a, b in evs])
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step / 1e3) / 1e6

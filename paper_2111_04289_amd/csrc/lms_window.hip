@@ -480,7 +480,7 @@ struct Lds {
   uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
 };
 
-enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_WORDS = 16 };
+enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_QMIN = 5, M_QMAX = 6, M_WORDS = 16 };
 
 __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   size_t b = 0;
@@ -543,6 +543,10 @@ __device__ __forceinline__ uint64_t combine(int fn, uint64_t x, uint64_t y) {
 
 template <int MA>
 __device__ void clear_tables(const WinArgs& a, Lds& s) {
+  if (threadIdx.x == 0) {
+    s.misc[M_QMIN] = ~0u;  // pane range of the groups, for the sliding composition
+    s.misc[M_QMAX] = 0;
+  }
   for (int i = threadIdx.x; i <= a.ek; i += kAggTPB) {
     s.keys[i] = kEmptyKey;
     s.kcnt[i] = 0;
@@ -846,41 +850,78 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
   const int nk = a.ek + 1;
   auto first_win = [&](int64_t q) { return fdiv(q - a.W, a.R, a.inv_R) + 1; };
   auto last_win = [&](int64_t q) { return fdiv(q, a.R, a.inv_R); };
+  uint32_t qlo = ~0u, qhi = 0;
   for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
     const uint64_t gid = s.gid[g];
-    if (gid != kEmptyGid) atomicAdd(&s.kcnt[(uint32_t)(gid >> 32)], 1u);
+    if (gid != kEmptyGid) {
+      atomicAdd(&s.kcnt[(uint32_t)(gid >> 32)], 1u);
+      qlo = min(qlo, (uint32_t)gid);
+      qhi = max(qhi, (uint32_t)gid);
+    }
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) {
+    qlo = min(qlo, (uint32_t)__shfl_xor((int)qlo, d, 64));
+    qhi = max(qhi, (uint32_t)__shfl_xor((int)qhi, d, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&s.misc[M_QMIN], qlo);
+    atomicMax(&s.misc[M_QMAX], qhi);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < nk; i += kAggTPB) s.kaux[i] = s.kcnt[i];
   __syncthreads();
   const uint32_t ng = block_scan_array<kAggTPB>(s.kaux, nk, s.scan);  // kaux = start of each key's run
   if (ng == 0) return;
-  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
-    const uint64_t gid = s.gid[g];
-    if (gid != kEmptyGid) {
+  const uint32_t qmin = s.misc[M_QMIN];
+  if (s.misc[M_QMAX] - qmin < 64) {
+    // All panes within 64 of each other: a pane's rank within its key is the
+    // number of the key's panes below it, read off a 64-bit pane mask per key
+    // (kept in the fw/wlo arrays, which are not needed until later).
+    uint64_t* const kbits = (uint64_t*)s.fw;  // nk words fit: 8 (ek + 1) <= 8 eg
+    for (int i = threadIdx.x; i < nk; i += kAggTPB) kbits[i] = 0;
+    __syncthreads();
+    for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
+      const uint64_t gid = s.gid[g];
+      if (gid != kEmptyGid) atomicOr((unsigned long long*)&kbits[(uint32_t)(gid >> 32)], 1ull << ((uint32_t)gid - qmin));
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
+      const uint64_t gid = s.gid[g];
+      if (gid == kEmptyGid) continue;
+      const uint32_t kid = (uint32_t)(gid >> 32), q = (uint32_t)gid;
+      const uint32_t r = (uint32_t)__popcll(kbits[kid] & ((1ull << (q - qmin)) - 1));
+      s.sorted[s.kaux[kid] + r] = ((uint64_t)q << 32) | (uint32_t)g;
+    }
+    __syncthreads();
+  } else {
+    for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {
+      const uint64_t gid = s.gid[g];
+      if (gid != kEmptyGid) {
+        const uint32_t kid = (uint32_t)(gid >> 32);
+        s.order[s.kaux[kid] + atomicAdd(&s.nwin[kid], 1u)] = (uint32_t)g;
+      }
+    }
+    __syncthreads();
+    int32_t* const wpane = s.wlo;  // panes of the unsorted key runs, only while ranking
+    for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) wpane[i] = (int32_t)(uint32_t)s.gid[s.order[i]];
+    __syncthreads();
+    for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {  // rank by pane within the key
+      const uint64_t gid = s.gid[g];
+      if (gid == kEmptyGid) continue;
       const uint32_t kid = (uint32_t)(gid >> 32);
-      s.order[s.kaux[kid] + atomicAdd(&s.nwin[kid], 1u)] = (uint32_t)g;
-    }
-  }
-  __syncthreads();
-  int32_t* const wpane = s.wlo;  // panes of the unsorted key runs, only while ranking
-  for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) wpane[i] = (int32_t)(uint32_t)s.gid[s.order[i]];
-  __syncthreads();
-  for (int g = threadIdx.x; g < a.eg; g += kAggTPB) {  // rank by pane within the key
-    const uint64_t gid = s.gid[g];
-    if (gid == kEmptyGid) continue;
-    const uint32_t kid = (uint32_t)(gid >> 32);
-    const int32_t q = (int32_t)(uint32_t)gid;
-    const uint32_t ks = s.kaux[kid], m = s.kcnt[kid];
-    uint32_t r = 0, j = 0;
-    for (; j + 8 <= m; j += 8) {
+      const int32_t q = (int32_t)(uint32_t)gid;
+      const uint32_t ks = s.kaux[kid], m = s.kcnt[kid];
+      uint32_t r = 0, j = 0;
+      for (; j + 8 <= m; j += 8) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) r += wpane[ks + j + u] < q;
+        for (int u = 0; u < 8; ++u) r += wpane[ks + j + u] < q;
+      }
+      for (; j < m; ++j) r += wpane[ks + j] < q;
+      s.sorted[ks + r] = ((uint64_t)(uint32_t)q << 32) | (uint32_t)g;
     }
-    for (; j < m; ++j) r += wpane[ks + j] < q;
-    s.sorted[ks + r] = ((uint64_t)(uint32_t)q << 32) | (uint32_t)g;
+    __syncthreads();
   }
-  __syncthreads();
   // Permute the group arrays (id, count, accumulators) into the sorted order,
   // one array at a time through registers, so the composition below reads a
   // key's consecutive panes from consecutive slots instead of through the slot

@@ -154,6 +154,21 @@ def test_window_agg_parity(n, length, slide, origin, key64, neg, nkeys, tspan):
     assert_window_equal(got, exp, aggs, f"n={n}")
 
 
+@pytest.mark.parametrize("tmax", [640, 650, 10])
+def test_window_agg_pane_span_at_mask_width(tmax):
+    """Panes 0..63 (span 63), 0..64 (span 64) and a single pane: the sliding
+    composition ranks a key's panes with a 64-bit mask up to span 63 and by
+    comparison beyond; both must give the oracle's result."""
+    n = 60000
+    rng = np.random.default_rng(tmax)
+    cols = [rng.integers(0, tmax, n, dtype=np.int64), rng.integers(0, 300, n, dtype=np.int64),
+            rng.integers(-1000, 1000, n, dtype=np.int32), rng.standard_normal(n).astype(np.float32)]
+    log(f"pane span tmax={tmax}")
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 50, 10, 0, AGGS5)
+    assert status == 0
+    assert_window_equal(got, oracle.window_agg(cols, 1, 0, 50, 10, 0, AGGS5), AGGS5, f"tmax={tmax}")
+
+
 def test_window_agg_zipf_hot_keys_pieces_and_merge():
     # one hot key carries ~12% of the rows: its partition is split into pieces and merged
     n = 1_000_000

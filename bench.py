@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--rows", type=int, default=1 << 24)
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 23)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-trace", action="store_true", help="time steps without per-kernel events")
+    ap.add_argument("--no-trace", action="store_true", help="skip the per-kernel timing pass")
+    ap.add_argument("--streams", type=int, default=3, choices=(1, 3),
+                    help="3: filter, window aggregation and join of a step on three forked streams; 1: one stream")
     ap.add_argument("--calib", action="store_true",
                     help="also run a 256 MiB device-to-device copy (scale reference for HBM byte counters)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-stream comparison")
@@ -227,10 +229,30 @@ def main():
     j_pay = torch.empty(n * mult, dtype=torch.int32, device=dev)
     j_cnt = torch.zeros(2, dtype=torch.int64, device=dev)
 
-    def step():
-        lms.lms_filter_project(cols, preds, [0, 1], [(2, 2, 0)], out=fp_out, d_count=fp_cnt, workspace=ws_fp)
-        lms.lms_window_agg(cols, 1, window, aggs, preds, groups=groups, d_count=wa_cnt, workspace=ws_wa)
-        lms.lms_hash_join(table, cols[1], cap=n * mult, out=(j_idx, j_pay), d_count=j_cnt, workspace=ws_j)
+    # The three operators read the same resident batch and share nothing else,
+    # so a step runs them on three streams (default priority) that fork from
+    # and join back into the current stream: one operator's small scan
+    # launches and tails overlap another's bandwidth-bound kernels.
+    side = [torch.cuda.Stream(device=dev) for _ in range(3)]
+    fork = torch.cuda.Event()
+    joins = [torch.cuda.Event() for _ in range(3)]
+
+    def step(concurrent=args.streams > 1):
+        sfp = swa = sj = None
+        if concurrent:
+            main = torch.cuda.current_stream()
+            fork.record(main)
+            for st in side:
+                st.wait_event(fork)
+            sfp, swa, sj = side
+        lms.lms_filter_project(cols, preds, [0, 1], [(2, 2, 0)], out=fp_out, d_count=fp_cnt, workspace=ws_fp,
+                               stream=sfp)
+        lms.lms_window_agg(cols, 1, window, aggs, preds, groups=groups, d_count=wa_cnt, workspace=ws_wa, stream=swa)
+        lms.lms_hash_join(table, cols[1], cap=n * mult, out=(j_idx, j_pay), d_count=j_cnt, workspace=ws_j, stream=sj)
+        if concurrent:
+            for st, ev in zip(side, joins):
+                ev.record(st)
+                main.wait_event(ev)
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -270,10 +292,10 @@ def main():
         evs[k][1].record(stream)
     torch.cuda.synchronize()
     trace = {}
-    if not args.no_trace:
+    if not args.no_trace:  # one stream here, so each kernel's time is its own
         lms.lms_trace_enable(True)
         for k in range(args.steps):
-            step()
+            step(concurrent=False)
         torch.cuda.synchronize()
         lms.lms_trace_enable(False)
         trace = lms.lms_trace_read()
@@ -339,7 +361,7 @@ def main():
                                "10 s window / 1 s slide, val < 314573, COUNT SUM MIN MAX AVG; "
                                "filter+project and 2^20-row static join on the same batch",
                    "rows": n, "groups": groups_n, "filter_rows": counts["filter_rows"],
-                   "join_pairs": counts["join_pairs"]},
+                   "join_pairs": counts["join_pairs"], "streams": args.streams},
         "p50_ms": round(float(np.percentile(step_ms, 50)), 4),
         "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
         "roofline": {"kernel": "window_agg (k_wa_* launch sequence)", "bound": "hbm",

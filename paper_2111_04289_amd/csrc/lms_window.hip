@@ -195,6 +195,9 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
 
 __global__ __launch_bounds__(kScanTPB) void k_wa_hist(WinArgs a) {
   extern __shared__ uint32_t hist[];
+  // the batch header is set here (nothing in this kernel reads it), which
+  // saves a launch before the histogram
+  if (blockIdx.x == 0 && threadIdx.x == 0) init_batch(a);
   const uint32_t w = xcd_chunk(blockIdx.x, (uint32_t)a.g1);
   if (w >= (uint32_t)a.g1) return;
   hist_chunk(a, w, hist);
@@ -1779,7 +1782,7 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
   int rc = setup_args(in, preds, npred, projs, nproj, key_col, w, aggs, nagg, out, d_count, workspace, ws_bytes, &a, &p);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)stream;
-  LMS_LAUNCH("k_wa_init", k_wa_init, dim3(1), dim3(64), 0, st, a);
+  if (in->nrows == 0) LMS_LAUNCH("k_wa_init", k_wa_init, dim3(1), dim3(64), 0, st, a);
   if (in->nrows > 0) {
     const size_t plds = (size_t)p.nparts * 4;
     LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);

@@ -384,6 +384,8 @@ __device__ __forceinline__ void staged_rows(const WinArgs& a, int v, const int64
 // in their place, so a selective predicate leaves most lines unread.
 template <int MA>
 __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
+  // eight value columns per row would hold too many loads in registers at 4 rows
+  constexpr int kU = MA <= 6 ? kUnroll : 2;
   for (int p = threadIdx.x; p < a.nparts; p += kScatterTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
   __syncthreads();
   const int64_t b0 = a.hdr[0];
@@ -394,32 +396,32 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
   const void* tc = a.q.col[a.ts_col];
   const int tdt = a.q.dt[a.ts_col];
   bool range_err = false;
-  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScatterTPB * kUnroll) {
-    bool ok[kUnroll];
-    int64_t key[kUnroll], ts[kUnroll], idx[kUnroll];
-    uint64_t val[kUnroll][MA];
+  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScatterTPB * kU) {
+    bool ok[kU];
+    int64_t key[kU], ts[kU], idx[kU];
+    uint64_t val[kU][MA];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kU; ++u) {
       idx[u] = b + (int64_t)u * kScatterTPB;
       ok[u] = idx[u] < hi;
     }
-    rows_pass<kUnroll>(a.q, idx, ok, lo);
-    load_i64_rows<kUnroll>(kc, kdt, idx, ok, lo, key);
-    load_i64_rows<kUnroll>(tc, tdt, idx, ok, lo, ts);
+    rows_pass<kU>(a.q, idx, ok, lo);
+    load_i64_rows<kU>(kc, kdt, idx, ok, lo, key);
+    load_i64_rows<kU>(tc, tdt, idx, ok, lo, ts);
 #pragma unroll
     for (int v = 0; v < MA; ++v) {
       if (v < a.nval) {
-        uint64_t x[kUnroll];
-        staged_rows<kUnroll>(a, v, idx, ok, lo, x);
+        uint64_t x[kU];
+        staged_rows<kU>(a, v, idx, ok, lo, x);
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) val[u][v] = x[u];
+        for (int u = 0; u < kU; ++u) val[u][v] = x[u];
       } else {
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) val[u][v] = 0;
+        for (int u = 0; u < kU; ++u) val[u][v] = 0;
       }
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
+    for (int u = 0; u < kU; ++u) {
       if (!ok[u]) continue;
       const uint32_t pos = atomicAdd(&cursor[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
       const int64_t rel = ts[u] - a.origin - b0 * a.pane;

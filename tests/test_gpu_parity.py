@@ -169,6 +169,22 @@ def test_window_agg_pane_span_at_mask_width(tmax):
     assert_window_equal(got, oracle.window_agg(cols, 1, 0, 50, 10, 0, AGGS5), AGGS5, f"tmax={tmax}")
 
 
+def test_window_agg_eight_accumulators():
+    """Eight aggregates, each with an accumulator of its own (the widest
+    instantiation of the kernels), over two input columns and a projection."""
+    n = 150001
+    cols = rand_cols(21, n, 700, 20000, neg=True)
+    aggs = [(SUM, 2), (MIN, 2), (MAX, 2), (AVG, 3), (SUM, 4), (MIN, 4), (MAX, 4), (AVG, 2)]
+    preds = [(2, LT, 500)]
+    projs = [(2, 3, -7)]
+    log("eight accumulators")
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 3000, 1000, 0, aggs, preds, projs)
+    assert status == 0
+    exp = oracle.window_agg(cols, 1, 0, 3000, 1000, 0, aggs, preds, projs)
+    assert cnt == len(exp["key"])
+    assert_window_equal(got, exp, aggs, "eight")
+
+
 def test_window_agg_zipf_hot_keys_pieces_and_merge():
     # one hot key carries ~12% of the rows: its partition is split into pieces and merged
     n = 1_000_000

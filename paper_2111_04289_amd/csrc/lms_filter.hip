@@ -45,88 +45,17 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// Quad path: when every column the filter reads starts on a 16-byte boundary,
-// lane l takes the four consecutive rows b + 4l .. b + 4l + 3 of a 256-row
-// quad, and loads them with one 16-byte load per 4-byte column (two per
-// 8-byte column), so a wave's load covers 1-2 KB instead of 256-512 B.
-// Measured on a plain 4-byte column scan: 6 TB/s with 16-byte loads against
-// 3.2 TB/s with per-row loads at the same bytes in flight.
+// Quad path (see the row quads of lms_internal.h): when every column the
+// filter reads starts on a 16-byte boundary, lane l takes rows b + 4l .. b +
+// 4l + 3 of each 256-row quad, kQuadSteps quads per step.
 constexpr int kQuadRows = 256;
 constexpr int kQuadSteps = 4;  // quads per step: their loads are in flight together
 constexpr int kStepRows = kQuadRows * kQuadSteps;
 static_assert(kWaveRows % kStepRows == 0, "wave tiles hold whole steps");
 
-// Raw 64-bit bits of the quads of a step (rows b0 + u * kQuadRows + 4 * lane
-// + e; column 16-byte aligned).  The column width is a template parameter, so
-// that a caller branches on it once around the loads and their uses: a branch
-// joining between the loads and their first use would make the wave wait for
-// each load before issuing the next.
-template <bool kWide>
-__device__ __forceinline__ void load_quads(const void* col, int64_t b0, int lane, uint64_t (&v)[kQuadSteps][4]) {
-  if constexpr (kWide) {
-    ulonglong2 x[kQuadSteps], y[kQuadSteps];
+__device__ __forceinline__ void step_quads(int64_t b0, int lane, int64_t (&r0)[kQuadSteps]) {
 #pragma unroll
-    for (int u = 0; u < kQuadSteps; ++u) {
-      const uint64_t* q = (const uint64_t*)col + b0 + u * kQuadRows + 4 * lane;
-      x[u] = *(const ulonglong2*)q;
-      y[u] = *(const ulonglong2*)(q + 2);
-    }
-#pragma unroll
-    for (int u = 0; u < kQuadSteps; ++u) {
-      v[u][0] = x[u].x;
-      v[u][1] = x[u].y;
-      v[u][2] = y[u].x;
-      v[u][3] = y[u].y;
-    }
-  } else {
-    uint4 x[kQuadSteps];
-#pragma unroll
-    for (int u = 0; u < kQuadSteps; ++u) x[u] = *(const uint4*)((const uint32_t*)col + b0 + u * kQuadRows + 4 * lane);
-#pragma unroll
-    for (int u = 0; u < kQuadSteps; ++u) {
-      v[u][0] = x[u].x;
-      v[u][1] = x[u].y;
-      v[u][2] = x[u].z;
-      v[u][3] = x[u].w;
-    }
-  }
-}
-
-__device__ __forceinline__ bool wide_dtype(int dt) { return dt == LMS_I64 || dt == LMS_F64; }
-
-// One predicate on a value's raw bits (the comparisons of rows_pass).
-__device__ __forceinline__ bool pred_bits(uint64_t b, int dt, int op, int64_t iv, double fv) {
-  switch (dt) {
-    case LMS_I32: return compare<int64_t>((int64_t)(int32_t)(uint32_t)b, op, iv);
-    case LMS_I64: return compare<int64_t>((int64_t)b, op, iv);
-    case LMS_F32: return compare<double>((double)__uint_as_float((uint32_t)b), op, fv);
-    default: return compare<double>(__longlong_as_double((long long)b), op, fv);
-  }
-}
-
-template <bool kWide>
-__device__ __forceinline__ void pred_quads(const Query& q, int k, int64_t b0, int lane, uint32_t (&m)[kQuadSteps]) {
-  const int c = q.pcol[k];
-  const int dt = q.dt[c], op = q.pop[k];
-  const int64_t iv = q.pival[k];
-  const double fv = q.pfval[k];
-  uint64_t v[kQuadSteps][4];
-  load_quads<kWide>(q.col[c], b0, lane, v);
-#pragma unroll
-  for (int u = 0; u < kQuadSteps; ++u)
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (!pred_bits(v[u][e], dt, op, iv, fv)) m[u] &= ~(1u << e);
-}
-
-// Pass masks (bit e: row b0 + u * kQuadRows + 4 * lane + e) of a step's quads.
-__device__ __forceinline__ void quads_pass(const Query& q, int64_t b0, int lane, uint32_t (&m)[kQuadSteps]) {
-#pragma unroll
-  for (int u = 0; u < kQuadSteps; ++u) m[u] = 0xF;
-  for (int k = 0; k < q.npred; ++k) {
-    if (wide_dtype(q.dt[q.pcol[k]])) pred_quads<true>(q, k, b0, lane, m);
-    else pred_quads<false>(q, k, b0, lane, m);
-  }
+  for (int u = 0; u < kQuadSteps; ++u) r0[u] = b0 + u * kQuadRows + 4 * lane;
 }
 
 __global__ __launch_bounds__(kTPB) void k_fp_count(FpArgs a) {
@@ -139,8 +68,10 @@ __global__ __launch_bounds__(kTPB) void k_fp_count(FpArgs a) {
   uint32_t mine = 0;  // quad path: this lane's passing rows
   if (a.quads) {
     for (; b0 + kStepRows <= hi; b0 += kStepRows) {
+      int64_t r0[kQuadSteps];
+      step_quads(b0, lane, r0);
       uint32_t m[kQuadSteps];
-      quads_pass(a.q, b0, lane, m);
+      quads_pass<kQuadSteps>(a.q, r0, m);
 #pragma unroll
       for (int u = 0; u < kQuadSteps; ++u) mine += (uint32_t)__popc(m[u]);
     }
@@ -191,14 +122,14 @@ __device__ __forceinline__ void put_bits(void* col, int dt, int64_t r, uint64_t 
 // (a kept column, or a projection's source with the projection applied, as
 // out_bits gives them) and writes the passing rows from output row r[u] on.
 template <bool kWide>
-__device__ __forceinline__ void write_quads(const FpArgs& a, int j, int64_t b0, int lane,
+__device__ __forceinline__ void write_quads(const FpArgs& a, int j, const int64_t (&r0)[kQuadSteps],
                                             const uint32_t (&m)[kQuadSteps], const int64_t (&r)[kQuadSteps]) {
   const bool kept = j < a.nkeep;
   const int p = j - a.nkeep;
   const int sc = kept ? a.keep[j] : a.q.prsrc[p];
   const int dt = a.q.dt[sc];
   uint64_t v[kQuadSteps][4];
-  load_quads<kWide>(a.q.col[sc], b0, lane, v);
+  load_quads<kWide, kQuadSteps>(a.q.col[sc], r0, v);
   if (!kept) {
     const uint64_t mul = (uint64_t)a.q.prmul[p], add = (uint64_t)a.q.pradd[p];
 #pragma unroll
@@ -244,8 +175,10 @@ __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
     // quad path: the lane's passing rows of quad u take consecutive outputs
     // from the lanes below it (their passing rows, all four slots) on
     for (; b0 + kStepRows <= hi; b0 += kStepRows) {
+      int64_t r0[kQuadSteps];
+      step_quads(b0, lane, r0);
       uint32_t m[kQuadSteps];
-      quads_pass(a.q, b0, lane, m);
+      quads_pass<kQuadSteps>(a.q, r0, m);
       int64_t r[kQuadSteps];
 #pragma unroll
       for (int u = 0; u < kQuadSteps; ++u) {
@@ -261,8 +194,8 @@ __global__ __launch_bounds__(kTPB) void k_fp_write(FpArgs a) {
       }
       for (int j = 0; j < ncol; ++j) {
         const int sc = j < a.nkeep ? a.keep[j] : a.q.prsrc[j - a.nkeep];
-        if (wide_dtype(a.q.dt[sc])) write_quads<true>(a, j, b0, lane, m, r);
-        else write_quads<false>(a, j, b0, lane, m, r);
+        if (wide_dtype(a.q.dt[sc])) write_quads<true>(a, j, r0, m, r);
+        else write_quads<false>(a, j, r0, m, r);
       }
     }
   }

@@ -60,6 +60,8 @@ struct PartInfo {
 struct WinArgs {
   Query q;
   int32_t key_col, ts_col;
+  int32_t quads;  // the predicate and key columns start on 16-byte boundaries
+  int32_t reserved_quads;
   int64_t len, slide, origin, pane, R, W;
   double inv_pane;
   double inv_R;
@@ -163,6 +165,23 @@ __device__ __forceinline__ uint32_t xcd_chunk(uint32_t g, uint32_t n) {
   return (g % kXcds) * c8 + g / kXcds;
 }
 
+constexpr int kHistQuads = 4;  // quads per thread per step of the histogram
+
+template <bool kWide>
+__device__ __forceinline__ void hist_quads(const WinArgs& a, const void* kc, const int64_t (&kr)[kHistQuads],
+                                           const uint32_t (&m)[kHistQuads], uint32_t* hist) {
+  uint64_t k[kHistQuads][4];
+  load_quads<kWide, kHistQuads>(kc, kr, k);
+#pragma unroll
+  for (int u = 0; u < kHistQuads; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if ((m[u] >> e) & 1u) {
+        const int64_t key = kWide ? (int64_t)k[u][e] : (int64_t)(int32_t)(uint32_t)k[u][e];
+        atomicAdd(&hist[part_of(fmix64((uint64_t)key), a.pbits)], 1u);
+      }
+}
+
 // LDS histogram of the passing rows of chunk w over the partitions.
 __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) hist[p] = 0;
@@ -171,9 +190,26 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
   const void* kc = a.q.col[a.key_col];
   const int kdt = a.q.dt[a.key_col];
+  int64_t b0 = lo;
+  if (a.quads) {
+    // row quads (see lms_internal.h): thread t takes rows 4t .. 4t + 3 of
+    // each 1024-row block, kHistQuads blocks per step; a quad with no passing
+    // row reads the chunk's first quad of keys instead of its own
+    for (; b0 + 1024 * kHistQuads <= hi; b0 += 1024 * kHistQuads) {
+      int64_t r0[kHistQuads], kr[kHistQuads];
+      uint32_t m[kHistQuads];
+#pragma unroll
+      for (int u = 0; u < kHistQuads; ++u) r0[u] = b0 + u * 1024 + 4 * threadIdx.x;
+      quads_pass<kHistQuads>(a.q, r0, m);
+#pragma unroll
+      for (int u = 0; u < kHistQuads; ++u) kr[u] = m[u] ? r0[u] : lo;
+      if (wide_dtype(kdt)) hist_quads<true>(a, kc, kr, m, hist);
+      else hist_quads<false>(a, kc, kr, m, hist);
+    }
+  }
   // kHistUnroll rows per thread per step; keys are loaded only for passing
   // rows, so a selective predicate leaves most key lines unread
-  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kHistUnroll) {
+  for (int64_t b = b0 + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kHistUnroll) {
     bool ok[kHistUnroll];
     int64_t key[kHistUnroll];
     int64_t idx[kHistUnroll];
@@ -1775,6 +1811,7 @@ int setup_args(const lms_batch* in, const lms_pred* preds, int32_t npred, const 
   carve_workspace(p, workspace, &a);
   a.key_col = key_col;
   a.ts_col = w->ts_col;
+  a.quads = preds_aligned(a.q) && ((uintptr_t)a.q.col[key_col] & 15) == 0 ? 1 : 0;
   a.len = w->len;
   a.slide = w->slide == 0 ? w->len : w->slide;
   a.origin = w->origin;

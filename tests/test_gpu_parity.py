@@ -169,6 +169,24 @@ def test_window_agg_pane_span_at_mask_width(tmax):
     assert_window_equal(got, oracle.window_agg(cols, 1, 0, 50, 10, 0, AGGS5), AGGS5, f"tmax={tmax}")
 
 
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_window_agg_column_views(offset):
+    """Columns that are views some rows into a buffer (not on a 16-byte
+    boundary unless offset is 0) take the row-by-row loads of the histogram
+    and scatter passes; results must not change."""
+    n = 120001
+    full = rand_cols(31 + offset, n + offset, 900, 30000, neg=True)
+    cols = [c[offset:] for c in full]
+    dcols = [c[offset:] for c in to_dev(full)]
+    log(f"window views offset={offset}")
+    preds = [(2, LT, 400)]
+    got, cnt, status = gpu_window_agg(cols, 1, 0, 5000, 1000, 7, AGGS5, preds, dev_cols=dcols)
+    assert status == 0
+    exp = oracle.window_agg(cols, 1, 0, 5000, 1000, 7, AGGS5, preds)
+    assert cnt == len(exp["key"])
+    assert_window_equal(got, exp, AGGS5, f"offset={offset}")
+
+
 def test_window_agg_eight_accumulators():
     """Eight aggregates, each with an accumulator of its own (the widest
     instantiation of the kernels), over two input columns and a projection."""

@@ -1139,11 +1139,12 @@ struct Segments {
 // starting with the whole range and halving a range whenever its groups do not
 // fit the LDS tables, then composes and emits its windows.
 template <int MA>
-__device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg) {
+__device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg, uint64_t rlo0 = 0,
+                                   uint64_t rhi0 = 1ull << 32) {
   const int64_t b0 = a.hdr[0];
   if (threadIdx.x == 0) {
-    s.stack[0] = 0;
-    s.stack[1] = 1ull << 32;
+    s.stack[0] = rlo0;
+    s.stack[1] = rhi0;
     s.misc[M_SSIZE] = 1;
   }
   __syncthreads();
@@ -1319,14 +1320,20 @@ __device__ void agg_item(const WinArgs& a, uint32_t item, char* lds_raw) {
 }
 
 template <int MA>
-__device__ void merge_part(const WinArgs& a, uint32_t p, char* lds_raw) {
+__device__ void merge_part(const WinArgs& a, uint32_t p, char* lds_raw, uint64_t rlo = 0, uint64_t rhi = 1ull << 32) {
   const PartInfo pi = a.pinfo[p];
   if (pi.kp <= 1) return;
   Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
   Segments sg{true, pi.start, pi.start + a.pfill[p]};
-  aggregate_and_emit<MA>(a, s, sg);
+  aggregate_and_emit<MA>(a, s, sg, rlo, rhi);
   __syncthreads();
 }
+
+// A split partition is merged as kMergeParts units, each taking the keys of
+// one part of the key-hash range (every unit reads all the partition's partial
+// records and inserts its own): the hottest partitions' merges then run on
+// several CUs instead of being the kernel's critical path.
+constexpr uint32_t kMergeParts = 4;
 
 // Claims the next unit of work from a device counter (one atomic per
 // workgroup; every workgroup of the launch is resident, so claiming in order
@@ -1352,8 +1359,11 @@ template <int MA>
 __global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wa_merge(WinArgs a) {
   extern __shared__ __align__(16) char lds_raw[];
   __shared__ uint32_t slot;
-  const uint32_t n = (uint32_t)a.hdr[4];
-  for (uint32_t j = claim(&a.hdr[3], &slot); j < n; j = claim(&a.hdr[3], &slot)) merge_part<MA>(a, a.splits[j], lds_raw);
+  const uint32_t n = (uint32_t)a.hdr[4] * kMergeParts;
+  for (uint32_t j = claim(&a.hdr[3], &slot); j < n; j = claim(&a.hdr[3], &slot)) {
+    const uint64_t part = (1ull << 32) / kMergeParts, r = j % kMergeParts;
+    merge_part<MA>(a, a.splits[j / kMergeParts], lds_raw, r * part, (r + 1) * part);
+  }
 }
 
 

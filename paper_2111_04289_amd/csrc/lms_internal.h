@@ -355,7 +355,7 @@ __device__ void tile_offsets(const int64_t* cnt, int64_t* off, int n, int64_t* t
   const int per = (n + TPB - 1) / TPB;
   const int lo = threadIdx.x * per;
   const int hi = min(n, lo + per);
-  constexpr int kHeld = 8;  // the first counts of the run are loaded together and kept
+  constexpr int kHeld = 16;  // the first counts of the run are loaded together and kept
   int64_t held[kHeld];
   int64_t s = 0;
 #pragma unroll

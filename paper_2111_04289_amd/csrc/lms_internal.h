@@ -242,9 +242,6 @@ __device__ __forceinline__ int64_t project(const Query& q, int j, int64_t i) {
 }
 
 // Extended columns: input columns followed by projections.
-__device__ __forceinline__ int ext_dtype(const Query& q, int c) {
-  return c < q.ncols ? q.dt[c] : q.dt[q.prsrc[c - q.ncols]];
-}
 __device__ __forceinline__ int64_t ext_i64(const Query& q, int c, int64_t i) {
   return c < q.ncols ? load_i64(q.col[c], q.dt[c], i) : project(q, c - q.ncols, i);
 }

@@ -90,7 +90,8 @@ def run_serving(args, log):
         eng = serve.Engine(data, mode=mode, model=model, log=log)
         res = eng.run()
         out[mode] = {k: res[k] for k in ("p50_ms", "p99_ms", "Mrows_s", "wall_s", "hbm_waits")}
-        out[mode]["queries"] = {q: {k: v[k] for k in ("p50_ms", "p99_ms", "maxlat_p99_ms", "batches", "cpu_batches")}
+        out[mode]["queries"] = {q: {k: v[k] for k in ("p50_ms", "p99_ms", "maxlat_p99_ms", "batches", "cpu_batches",
+                                                      "breakdown_pct")}
                                 for q, v in res["queries"].items()}
         log(f"serving {mode}: {json.dumps(res)}")
         del eng

@@ -168,6 +168,12 @@ class Query:
         self.maxlat = []        # per-batch MaxLat (ms)
         self.proc = []
         self.batch_rows = []
+        # time spent per step, as in the paper's overhead breakdown (ms):
+        # datasets buffered before admission, host time in the admission
+        # controller and in MapDevice
+        self.t_buffer = 0.0
+        self.t_construct = 0.0
+        self.t_map = 0.0
         self.cpu_batches = 0
         self.rows_done = 0
         self.results = [] if eng.collect else None
@@ -349,6 +355,7 @@ class Engine:
             maxlat = float(lat.max())
             q.maxlat.append(maxlat)
             q.proc.append(b.t_done - b.t_admit)
+            q.t_buffer += max(0.0, b.t_admit - b.oldest)
             q.batch_rows.append(b.rows)
             q.rows_done += b.rows
             if self.mode == "served":
@@ -385,7 +392,9 @@ class Engine:
                     if q.closed or len(q.inflight) + len(q.waiting) >= self.slots:
                         continue
                     new = arr[q.next_ds:arrived]
+                    t0 = time.perf_counter()
                     d = q.ctl.poll(now, new, np.full(len(new), DS_ROWS, np.int64))
+                    q.t_construct += (time.perf_counter() - t0) * 1e3
                     q.next_ds = arrived
                     if d.admit:
                         d0 = q.next_batch_ds
@@ -393,7 +402,9 @@ class Engine:
                         q.next_batch_ds = d1
                         b = Batch(q.name, d0, d1, (d1 - d0) * DS_ROWS, now, float(arr[d0]))
                         b.need = q.need(b.rows)
+                        t0 = time.perf_counter()
                         b.device = self.place(q, b.rows, (now - last_admit[q.name]) / 1e3)
+                        q.t_map += (time.perf_counter() - t0) * 1e3
                         last_admit[q.name] = now
                         q.waiting.append(b)
             elif self.mode == "baseline" and now >= next_trigger and not any(
@@ -452,6 +463,17 @@ class Engine:
         return self.report(end_ms)
 
     def report(self, end_ms):
+        def breakdown(q):
+            # shares of the query's time (the paper's overhead breakdown):
+            # buffering before admission, the admission controller, MapDevice,
+            # processing (admission to result on the host), and blocking on an
+            # asynchronous optimizer -- zero here: the placement model is
+            # evaluated synchronously, in microseconds
+            parts = {"buffering": q.t_buffer, "construct_micro_batch": q.t_construct, "map_device": q.t_map,
+                     "processing": float(np.sum(q.proc)) if q.proc else 0.0, "optimization_blocking": 0.0}
+            tot = sum(parts.values()) or 1.0
+            return {k: round(100.0 * v / tot, 3) for k, v in parts.items()}
+
         out = {"mode": self.mode, "stream_ms": round(end_ms, 1), "queries": {}}
         total = 0
         wall = self.now()
@@ -465,7 +487,8 @@ class Engine:
                 "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
                 "maxlat_p50_ms": round(float(np.percentile(ml, 50)), 2),
                 "maxlat_p99_ms": round(float(np.percentile(ml, 99)), 2),
-                "mean_proc_ms": round(float(np.mean(q.proc)), 3) if q.proc else 0.0}
+                "mean_proc_ms": round(float(np.mean(q.proc)), 3) if q.proc else 0.0,
+                "breakdown_pct": breakdown(q)}
         out["rows_per_query"] = total // max(1, len(self.queries))
         out["Mrows_s"] = round(total / max(1, len(self.queries)) / (wall / 1e3) / 1e6, 3)
         out["wall_s"] = round(wall / 1e3, 2)

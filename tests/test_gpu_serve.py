@@ -85,6 +85,14 @@ def test_results_alone_and_in_mix_equal_the_oracle(serve, stream):
     check_join(mix, data, cols)
     info = mix.queries["slide"].state.info()
     assert info["late_rows"] == 0 and info["dropped_rows"] == 0
+    # the overhead breakdown: shares of buffering, admission, MapDevice,
+    # processing and optimizer blocking, which sum to 100 %
+    for q, v in res["queries"].items():
+        bd = v["breakdown_pct"]
+        assert set(bd) == {"buffering", "construct_micro_batch", "map_device", "processing",
+                           "optimization_blocking"}, q
+        assert abs(sum(bd.values()) - 100.0) < 0.01 and bd["processing"] > 0 and bd["buffering"] > 0, (q, bd)
+        assert bd["construct_micro_batch"] > 0 and bd["map_device"] >= 0 and bd["optimization_blocking"] == 0, (q, bd)
 
 
 def test_plain_trigger_form_and_cpu_placement(serve, stream):

@@ -189,7 +189,7 @@ def run_batched(args, torch, lms, datagen, cols, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
     import torch
 

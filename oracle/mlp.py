@@ -7,7 +7,9 @@ network, written from the definition of the masked squared error
 
 with the parameter layout W1[64][12], b1[64], W2[64][64], b2[64], W3[2][64],
 b3[2] flattened in that order.  Pinned in tests by central finite
-differences of `loss`.
+differences of `loss`, and against torch's CPU linear layers, autograd and
+Adam optimizer in float64 (forward pass, gradient, update), with planted
+mistakes that the pins must reject.
 """
 from __future__ import annotations
 

@@ -55,7 +55,7 @@ extern "C" {
 #define LMS_EINVAL -1    /* bad argument: null pointer, bad dtype/column index, slide > len, cap too small ... */
 #define LMS_EHIP -2      /* a HIP runtime call or kernel launch failed */
 #define LMS_ENOMEM -3    /* workspace too small or a library allocation failed */
-#define LMS_ECAPACITY -4 /* device: a key has more distinct panes than one partition table holds */
+#define LMS_ECAPACITY -4 /* device: a table is too small (e.g. one window of one key spans more panes than a workgroup table holds) */
 #define LMS_ERANGE -5    /* device: an event time lies about 2^30 panes or more from the batch's first row */
 
 typedef void* lms_stream; /* hipStream_t */
@@ -163,18 +163,43 @@ int lms_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred
  * Groups the rows that pass the predicates by (cols[key_col], window) and
  * computes aggs[0..nagg) per group.  The key column must be integer.  Output
  * rows go to `out` (see lms_groups); d_count[0] receives the number of groups,
- * of which min(count, out->cap) are written.  d_count[1] is LMS_ECAPACITY if
- * a single key holds more distinct panes (pane = gcd(len, slide)) than one
- * workgroup table can hold (see lms_window_agg_pane_limit), LMS_ERANGE if an
+ * of which min(count, out->cap) are written.  d_count[1] is LMS_ECAPACITY
+ * only if the passing rows of one key fill more distinct panes (pane =
+ * gcd(len, slide)) inside a single window than one workgroup table holds
+ * (lms_window_agg_pane_limit; a key with more panes than that in all is
+ * aggregated in several passes over ranges of its windows), LMS_ERANGE if an
  * event time is 2^30 - slide/pane panes or more before, or 2^30 panes or more
  * after, the first row's pane.
- * Workspace: lms_window_agg_workspace() with the same arguments. */
+ * Workspace: lms_window_agg_workspace() with the same arguments.  After the
+ * call completes the workspace still holds the rows it staged and their
+ * partial aggregates; lms_window_agg_emit can then write the same groups
+ * again. */
 size_t lms_window_agg_workspace(const lms_batch* in, int32_t key_col, const lms_window* w, const lms_agg* aggs,
                                 int32_t nagg);
+/* Most non-empty panes one key may hold inside a single window for nagg
+ * aggregates (the (key, pane) slots of one workgroup table). */
 int64_t lms_window_agg_pane_limit(int32_t nagg);
 int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs, int32_t nproj,
                    int32_t key_col, const lms_window* w, const lms_agg* aggs, int32_t nagg, const lms_groups* out,
                    int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream);
+
+/* Re-emission (same operation: Table II "Aggregation (Hash)"): writes the
+ * groups of the last lms_window_agg call that used `workspace` into `out`
+ * again, from the staged rows and partial aggregates that call left in the
+ * workspace -- the input columns are not read (they may already be freed).
+ * This is how a caller whose first output capacity was below d_count[0]
+ * obtains every group without re-running the scan: allocate d_count[0] rows
+ * and emit again.  `out` must hold nagg aggregate columns of the original
+ * call's types, in its order; d_count as for lms_window_agg ([1] carries the
+ * original call's device status).  The workspace must be untouched since
+ * that call, and neither that call nor another use of the workspace may still
+ * run (stream order or events).  Returns LMS_EINVAL for bad arguments; a
+ * workspace that no call filled, another nagg or a moved workspace set
+ * d_count[1] = LMS_EINVAL on the device.  Asynchronous and stream-ordered;
+ * performs no allocation.  Row order is unspecified and may differ from the
+ * first emission. */
+int lms_window_agg_emit(const lms_groups* out, int32_t nagg, int64_t* d_count, void* workspace, size_t ws_bytes,
+                        lms_stream stream);
 
 /* ---- Many micro-batches per launch -------------------------------------------
  * The same windowed group-by over nbatch micro-batches of one schema, with

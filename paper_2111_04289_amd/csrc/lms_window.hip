@@ -61,7 +61,7 @@ struct WinArgs {
   Query q;
   int32_t key_col, ts_col;
   int32_t quads;  // the predicate and key columns start on 16-byte boundaries
-  int32_t reserved_quads;
+  int32_t emit_only;  // re-emission from an intact workspace: split pieces keep their partial records
   int64_t len, slide, origin, pane, R, W;
   double inv_pane;
   double inv_R;
@@ -77,7 +77,11 @@ struct WinArgs {
   int32_t pbits, nparts, g1, max_items, ek, eg;
   int64_t chunk, rs;
   // workspace
-  int64_t* hdr;  // [0] base pane B0, [1] items, [2]/[3] work counters, [4] split partitions
+  // [0] base pane B0, [1] items, [2]/[3] work counters, [4] split partitions,
+  // [5] device status of the call, [6] kSavedMagic once `saved` holds the
+  // call's arguments, [7] 1 while a re-emission's arguments are valid
+  int64_t* hdr;
+  struct WinArgs* saved;  // [0] the call's own arguments, [1] those of a re-emission
   uint32_t* splits;  // nparts: the partitions split into pieces, in claim order
   uint32_t* H;
   uint32_t* Off;
@@ -139,6 +143,7 @@ __device__ __forceinline__ void init_batch(const WinArgs& a) {
     a.hdr[2] = 0;  // next aggregation item to claim
     a.hdr[3] = 0;  // next split partition to claim for merging
     a.hdr[4] = 0;  // split partitions
+    a.hdr[5] = 0;  // status
     int64_t b0 = 0;
     if (a.q.nrows > 0) {
       const int64_t ts0 = load_i64(a.q.col[a.ts_col], a.q.dt[a.ts_col], 0);
@@ -149,8 +154,29 @@ __device__ __forceinline__ void init_batch(const WinArgs& a) {
   }
 }
 
+// Marks a workspace whose `saved` slot holds the arguments of the call that
+// filled it (lms_window_agg_emit re-emits from such a workspace).
+constexpr int64_t kSavedMagic = 0x4c4d5357494e4147ll;
+// Byte offset of the `saved` slot: the header takes the first 256 bytes.
+constexpr size_t kSavedOff = 256;
+
+// Device status of a call: the caller's d_count[1], and the workspace header
+// for a later re-emission.
+__device__ __forceinline__ void win_status(const WinArgs& a, int code) {
+  set_device_status(a.d_count, code);
+  atomicMin((long long*)&a.hdr[5], (long long)code);
+}
+
+__device__ __forceinline__ void save_args(const WinArgs& a) {
+  *a.saved = a;
+  a.hdr[6] = kSavedMagic;
+}
+
 __global__ void k_wa_init(WinArgs a) {
-  if (threadIdx.x == 0) init_batch(a);
+  if (threadIdx.x == 0) {
+    init_batch(a);
+    save_args(a);
+  }
 }
 
 // Chunk processed by workgroup slot g of a launch over n chunks (slots padded
@@ -387,6 +413,7 @@ __global__ __launch_bounds__(kPlanTPB) void k_wa_scanp(WinArgs a) {
   __shared__ uint32_t r[kMaxParts], st[kMaxParts], kc[kMaxParts], base[kMaxParts];
   __shared__ uint32_t scratch[kPlanTPB / 64 + 1];
   plan_items(a, r, st, kc, base, scratch);
+  if (threadIdx.x == 0) save_args(a);
 }
 
 // Per-(partition, chunk) write offsets: partition start plus an exclusive scan
@@ -531,7 +558,7 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
         if (t < nw) *(uint2*)(r + a.pane_off + 4 * t) = make_uint2(wd[t], wd[t + 1]);
     }
   }
-  if (range_err) set_device_status(a.d_count, LMS_ERANGE);
+  if (range_err) win_status(a, LMS_ERANGE);
   __syncthreads();
 }
 
@@ -569,10 +596,10 @@ struct Lds {
   int32_t* wlo;     // eg: first window owned by the sorted entry
   uint32_t* scan;  // kAggTPB / 64 + 1
   uint32_t* misc;  // flags and broadcasts
-  uint64_t* stack; // 2 * kStackCap: hash intervals still to aggregate
+  uint64_t* stack; // 4 * kStackCap: (hash lo, hash hi, anchor lo, anchor hi) still to aggregate
 };
 
-enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_QMIN = 5, M_QMAX = 6,
+enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_QMIN = 5, M_QMAX = 6, M_PLO = 7, M_PHI = 8,
        // sliding emission: output pointers (okey, ows, oagg[]) and per-aggregate codes
        M_OUT = 16, M_CODE = M_OUT + 2 * (2 + kMaxAggs), M_WORDS = M_CODE + kMaxAggs };
 
@@ -582,7 +609,7 @@ __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   b += 3 * align_up((size_t)(ek + 1) * 4, 16);
   b += (size_t)eg * 8 + (size_t)nacc * eg * 8 + (size_t)eg * 4 + (size_t)eg * 4 + (size_t)eg * 8 + (size_t)eg * 8;
   b += align_up((kAggTPB / 64 + 1) * 4, 16) + M_WORDS * 4;
-  b += 2 * kStackCap * 8;
+  b += 4 * kStackCap * 8;
   return b;
 }
 
@@ -992,9 +1019,11 @@ __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, u
 // pane's last window.  Output rows are then produced one per thread, so
 // consecutive threads write consecutive rows: row r belongs to the last entry
 // whose owned windows start at or before r, and its window holds that entry's
-// pane and the key's following panes whose first window is not later.
+// pane and the key's following panes whose first window is not later.  Only
+// windows [wmin, wmax] are emitted (the windows whose first pane lies in the
+// anchor range of the tables' current pass).
 template <int MA>
-__device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
+__device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0, int64_t wmin, int64_t wmax) {
   fill_out_table(a, s);  // the barriers below publish it
   const int nk = a.ek + 1;
   auto first_win = [&](int64_t q) { return fdiv(q - a.W, a.R, a.inv_R) + 1; };
@@ -1102,8 +1131,8 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0) {
     const int64_t q = (int64_t)(v >> 32);
     const uint32_t kid = (uint32_t)(s.gid[i] >> 32);
     const int64_t fw = first_win(q);
-    const int64_t hi = last_win(q);
-    int64_t lo = fw;
+    const int64_t hi = min(last_win(q), wmax);
+    int64_t lo = max(fw, wmin);
     if (i > s.kaux[kid]) lo = max(lo, last_win((int64_t)(s.sorted[i - 1] >> 32)) + 1);
     s.fw[i] = (int32_t)fw;
     s.wlo[i] = (int32_t)lo;
@@ -1178,22 +1207,39 @@ struct Segments {
 
 // Aggregates every element whose key hash lies in sub-ranges of [0, 2^32),
 // starting with the whole range and halving a range whenever its groups do not
-// fit the LDS tables, then composes and emits its windows.
+// fit the LDS tables, then composes and emits its windows.  A range of a single
+// hash value that still overflows (one key holding more panes than a table) is
+// split by window anchor instead: a pass over anchors [elo, ehi) emits the
+// windows whose first pane lies there, and inserts the panes those windows
+// span, [elo, ehi + W - 1); the anchor range is halved until it fits, so only
+// a single window spanning more panes than a table holds is LMS_ECAPACITY.
+constexpr int64_t kAnyLo = INT64_MIN, kAnyHi = INT64_MAX;  // no anchor restriction
+
 template <int MA>
 __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg, uint64_t rlo0 = 0,
                                    uint64_t rhi0 = 1ull << 32) {
   const int64_t b0 = a.hdr[0];
+  auto push = [&](uint32_t n, uint64_t rlo, uint64_t rhi, int64_t elo, int64_t ehi) {
+    s.stack[4 * n] = rlo;
+    s.stack[4 * n + 1] = rhi;
+    s.stack[4 * n + 2] = (uint64_t)elo;
+    s.stack[4 * n + 3] = (uint64_t)ehi;
+  };
   if (threadIdx.x == 0) {
-    s.stack[0] = rlo0;
-    s.stack[1] = rhi0;
+    push(0, rlo0, rhi0, kAnyLo, kAnyHi);
     s.misc[M_SSIZE] = 1;
   }
   __syncthreads();
   while (true) {
     const uint32_t ssize = s.misc[M_SSIZE];
     if (ssize == 0) break;
-    const uint64_t rlo = s.stack[2 * (ssize - 1)];
-    const uint64_t rhi = s.stack[2 * (ssize - 1) + 1];
+    const uint64_t rlo = s.stack[4 * (ssize - 1)];
+    const uint64_t rhi = s.stack[4 * (ssize - 1) + 1];
+    const int64_t elo = (int64_t)s.stack[4 * (ssize - 1) + 2];
+    const int64_t ehi = (int64_t)s.stack[4 * (ssize - 1) + 3];
+    const bool any = elo == kAnyLo;
+    // panes inserted in this pass: [elo, ehi + W - 1) unless unrestricted
+    const int64_t ilo = any ? kAnyLo : elo, ihi = any ? kAnyHi : ehi + a.W - 1;
     __syncthreads();
     if (threadIdx.x == 0) {
       s.misc[M_SSIZE] = ssize - 1;
@@ -1220,7 +1266,8 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg,
           if (!sg.partial) finish_row<MA>(a, cur);
           const uint64_t h = fmix64((uint64_t)cur.key);
           const uint32_t sh = subhash(h);
-          if (sh >= rlo && sh < rhi) {
+          const int64_t q = (int64_t)cur.pane;
+          if (sh >= rlo && sh < rhi && q >= ilo && q < ihi) {
             if (!insert<MA>(a, s, cur, h)) s.misc[M_OVF] = 1;
           }
         }
@@ -1236,24 +1283,62 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg,
     }
     __syncthreads();
     if (ovf) {
+      const bool split_hash = rhi - rlo > 1;
+      if (!split_hash && any) {
+        // pane bounds of this hash range: the anchors of its windows span
+        // [min pane - W + 1, max pane]
+        if (threadIdx.x == 0) {
+          s.misc[M_PLO] = ~0u;
+          s.misc[M_PHI] = 0;
+        }
+        __syncthreads();
+        uint32_t qlo = ~0u, qhi = 0;
+        for (uint32_t e = sg.lo + threadIdx.x; e < sg.hi; e += kAggTPB) {
+          const int64_t key = sg.partial ? a.pkey[e] : *(const int64_t*)(a.srec + (size_t)e * a.rec);
+          const uint32_t q = sg.partial ? a.ppane[e] : *(const uint32_t*)(a.srec + (size_t)e * a.rec + a.pane_off);
+          const uint32_t sh = subhash(fmix64((uint64_t)key));
+          if (sh >= rlo && sh < rhi) {
+            qlo = min(qlo, q);
+            qhi = max(qhi, q);
+          }
+        }
+        atomicMin(&s.misc[M_PLO], qlo);
+        atomicMax(&s.misc[M_PHI], qhi);
+        __syncthreads();
+      }
       if (threadIdx.x == 0) {
         const uint32_t n = s.misc[M_SSIZE];
-        if (rhi - rlo <= 1 || n + 2 > kStackCap) {
-          set_device_status(a.d_count, LMS_ECAPACITY);
-        } else {
+        int64_t nlo = elo, nhi = ehi;
+        if (!split_hash && any) {
+          nlo = (int64_t)s.misc[M_PLO] - a.W + 1;
+          nhi = (int64_t)s.misc[M_PHI] + 1;
+        }
+        if (n + 2 > kStackCap || (!split_hash && nhi - nlo <= 1)) {
+          win_status(a, LMS_ECAPACITY);
+          s.misc[M_SSIZE] = 0;  // the call's result is void: the item stops here
+        } else if (split_hash) {
           const uint64_t mid = rlo + (rhi - rlo) / 2;
-          s.stack[2 * n] = rlo;
-          s.stack[2 * n + 1] = mid;
-          s.stack[2 * n + 2] = mid;
-          s.stack[2 * n + 3] = rhi;
+          push(n, rlo, mid, elo, ehi);
+          push(n + 1, mid, rhi, elo, ehi);
+          s.misc[M_SSIZE] = n + 2;
+        } else {
+          const int64_t mid = nlo + (nhi - nlo) / 2;
+          push(n, rlo, rhi, nlo, mid);
+          push(n + 1, rlo, rhi, mid, nhi);
           s.misc[M_SSIZE] = n + 2;
         }
       }
       __syncthreads();
       continue;
     }
-    if (a.R == 1 && a.W == 1) emit_tumbling<MA>(a, s, b0);
-    else emit_sliding<MA>(a, s, b0);
+    if (a.R == 1 && a.W == 1) {
+      emit_tumbling<MA>(a, s, b0);  // the inserted panes are exactly the windows to emit
+    } else {
+      // windows w whose first pane w * R lies in [elo, ehi)
+      const int64_t wmin = any ? INT64_MIN : fdiv(elo + a.R - 1, a.R, a.inv_R);
+      const int64_t wmax = any ? INT64_MAX : fdiv(ehi + a.R - 1, a.R, a.inv_R) - 1;
+      emit_sliding<MA>(a, s, b0, wmin, wmax);
+    }
     __syncthreads();
   }
 }
@@ -1352,7 +1437,7 @@ __device__ void agg_item(const WinArgs& a, uint32_t item, char* lds_raw) {
   Lds s = carve_lds(lds_raw, a.ek, a.eg, a.nacc);
   const Item it = a.items[item];
   if (it.kp > 1) {
-    aggregate_piece<MA>(a, s, it);
+    if (!a.emit_only) aggregate_piece<MA>(a, s, it);  // a re-emission merges the records flushed before
   } else {
     Segments sg{false, it.lo, it.hi};
     aggregate_and_emit<MA>(a, s, sg);
@@ -1598,6 +1683,82 @@ __global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wam_merge(const char
   }
 }
 
+// ---- re-emission from an intact workspace --------------------------------------
+//
+// The staged records, the item plan and the split partitions' partial records
+// stay in the workspace after a call, so its groups can be emitted again into
+// other outputs without reading the input columns: the aggregation items are
+// re-run (pieces excepted: their partial records are already flushed) and the
+// split partitions merged again.
+
+struct EmitOut {
+  int64_t* okey;
+  int64_t* ows;
+  void* oagg[kMaxAggs];
+  int64_t cap;
+  int64_t* d_count;
+  int32_t nagg;
+  int32_t reserved;
+};
+
+__global__ void k_wa_emit_init(char* ws, EmitOut o) {
+  if (threadIdx.x != 0) return;
+  int64_t* const hdr = (int64_t*)ws;
+  WinArgs* const sv = (WinArgs*)(ws + kSavedOff);
+  o.d_count[0] = 0;
+  const bool ok = hdr[6] == kSavedMagic && sv->hdr == hdr && sv->nagg == o.nagg;
+  hdr[7] = ok ? 1 : 0;
+  if (!ok) {
+    o.d_count[1] = LMS_EINVAL;
+    return;
+  }
+  o.d_count[1] = hdr[5];  // the status the call's own kernels set
+  WinArgs* const ea = sv + 1;
+  *ea = *sv;
+  ea->okey = o.okey;
+  ea->ows = o.ows;
+  for (int k = 0; k < kMaxAggs; ++k) ea->oagg[k] = o.oagg[k];
+  ea->cap = o.cap;
+  ea->d_count = o.d_count;
+  ea->emit_only = 1;
+  hdr[2] = 0;
+  hdr[3] = 0;
+}
+
+// The re-emission's arguments, copied into the workgroup's LDS.
+__device__ __forceinline__ bool load_emit_args(const char* ws, WinArgs* sa) {
+  if (((const int64_t*)ws)[7] != 1) return false;
+  const uint32_t* src = (const uint32_t*)((const WinArgs*)(ws + kSavedOff) + 1);
+  uint32_t* dst = (uint32_t*)sa;
+  for (uint32_t i = threadIdx.x; i < sizeof(WinArgs) / 4; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  return true;
+}
+
+template <int MA>
+__global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wa_agg_again(const char* ws) {
+  extern __shared__ __align__(16) char lds_raw[];
+  __shared__ WinArgs sa;
+  __shared__ uint32_t slot;
+  if (!load_emit_args(ws, &sa)) return;
+  const uint32_t n = (uint32_t)sa.hdr[1];
+  for (uint32_t item = claim(&sa.hdr[2], &slot); item < n; item = claim(&sa.hdr[2], &slot))
+    agg_item<MA>(sa, item, lds_raw);
+}
+
+template <int MA>
+__global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wa_merge_again(const char* ws) {
+  extern __shared__ __align__(16) char lds_raw[];
+  __shared__ WinArgs sa;
+  __shared__ uint32_t slot;
+  if (!load_emit_args(ws, &sa)) return;
+  const uint32_t n = (uint32_t)sa.hdr[4] * kMergeParts;
+  for (uint32_t j = claim(&sa.hdr[3], &slot); j < n; j = claim(&sa.hdr[3], &slot)) {
+    const uint64_t part = (1ull << 32) / kMergeParts, r = j % kMergeParts;
+    merge_part<MA>(sa, sa.splits[j / kMergeParts], lds_raw, r * part, (r + 1) * part);
+  }
+}
+
 // ---- host planning -------------------------------------------------------------
 
 int64_t next_pow2(int64_t x) {
@@ -1673,6 +1834,7 @@ Plan make_plan(int64_t n, int nval, int nacc) {
 size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   WsCarver c(base);
   int64_t* hdr = c.take<int64_t>(8);
+  WinArgs* saved = c.take<WinArgs>(2);  // at kSavedOff
   uint32_t* splits = c.take<uint32_t>(p.nparts);
   uint32_t* H = c.take<uint32_t>((size_t)p.nparts * p.g1);
   uint32_t* Off = c.take<uint32_t>((size_t)p.nparts * p.g1);
@@ -1688,6 +1850,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   for (int k = 0; k < p.nacc; ++k) pacc[k] = c.take<uint64_t>(p.n);
   if (a) {
     a->hdr = hdr;
+    a->saved = saved;
     a->splits = splits;
     a->H = H;
     a->Off = Off;
@@ -1956,6 +2119,49 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
     else launch_tail<8>(p, a, plds, st);
   }
   return check_hip(hipGetLastError(), "window_agg launch");
+}
+
+extern "C" int lms_window_agg_emit(const lms_groups* out, int32_t nagg, int64_t* d_count, void* workspace,
+                                   size_t ws_bytes, lms_stream stream) {
+  if (!out) return set_error(LMS_EINVAL, "output groups is NULL");
+  if (out->cap < 0) return set_error(LMS_EINVAL, "negative output capacity");
+  if (out->cap > 0 && (!out->key || !out->wstart)) return set_error(LMS_EINVAL, "output key/wstart is NULL");
+  if (nagg < 0 || nagg > kMaxAggs) return set_error(LMS_EINVAL, "nagg %d outside [0, %d]", nagg, kMaxAggs);
+  if (nagg > 0 && !out->aggs) return set_error(LMS_EINVAL, "output aggs is NULL");
+  for (int k = 0; k < nagg; ++k)
+    if (out->cap > 0 && !out->aggs[k]) return set_error(LMS_EINVAL, "output aggregate %d is NULL", k);
+  if (!d_count) return set_error(LMS_EINVAL, "d_count is NULL");
+  if (!workspace || ws_bytes < kSavedOff + 2 * sizeof(WinArgs))
+    return set_error(LMS_EINVAL, "workspace is not one a lms_window_agg call filled");
+  static const int attr_rc = [] {
+    int rc = check_hip(hipFuncSetAttribute((const void*)k_wa_agg_again<kMaxAggs>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit - kArgsLds),
+                       "LDS attribute");
+    if (!rc)
+      rc = check_hip(hipFuncSetAttribute((const void*)k_wa_merge_again<kMaxAggs>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, kLdsLimit - kArgsLds),
+                     "LDS attribute");
+    return rc;
+  }();
+  if (attr_rc) return attr_rc;
+  EmitOut o{};
+  o.okey = out->key;
+  o.ows = out->wstart;
+  for (int k = 0; k < nagg; ++k) o.oagg[k] = out->aggs[k];
+  o.cap = out->cap;
+  o.d_count = d_count;
+  o.nagg = nagg;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  // the kernels take the accumulator count from the saved arguments, so the
+  // widest unroll serves every call
+  const int resident = num_cus();
+  LMS_LAUNCH("k_wa_emit_init", k_wa_emit_init, dim3(1), dim3(64), 0, st, ws, o);
+  LMS_LAUNCH("k_wa_agg_again", k_wa_agg_again<kMaxAggs>, dim3(resident), dim3(kAggTPB), kLdsLimit - kArgsLds, st,
+             (const char*)ws);
+  LMS_LAUNCH("k_wa_merge_again", k_wa_merge_again<kMaxAggs>, dim3(resident), dim3(kAggTPB), kLdsLimit - kArgsLds,
+             st, (const char*)ws);
+  return check_hip(hipGetLastError(), "window_agg_emit launch");
 }
 
 extern "C" int lms_set_tuning(const lms_tuning* t) {

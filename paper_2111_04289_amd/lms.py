@@ -140,6 +140,7 @@ _SIGS = {
     "lms_window_agg_pane_limit": (_i64, [_i32]),
     "lms_window_agg": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _i32, _P(lms_window),
                                       _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz, _vp]),
+    "lms_window_agg_emit": (ctypes.c_int, [_P(lms_groups), _i32, _vp, _vp, _sz, _vp]),
     "lms_window_agg_multi_workspace": (_sz, [_P(lms_batch), _i32, _i32, _P(lms_window), _P(lms_agg), _i32]),
     "lms_window_agg_multi_prepare": (ctypes.c_int, [_P(lms_batch), _i32, _P(lms_pred), _i32, _P(lms_proj), _i32, _i32,
                                                     _P(lms_window), _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz,
@@ -252,7 +253,10 @@ def _projs(projs):
 
 
 class Workspace:
-    """A grow-only device scratch buffer for the operators."""
+    """A grow-only device scratch buffer for the operators.
+
+    Calls that may overlap in time need workspaces of their own (lms.h).
+    """
 
     def __init__(self, device=None):
         self.device = device or torch.device("cuda")
@@ -264,13 +268,33 @@ class Workspace:
         return self.buf
 
 
+# one default workspace per (device, stream): calls on one stream never
+# overlap, calls on different streams never share one
 _default_ws: dict = {}
 
 
-def _ws(workspace, nbytes, device):
+def _torch_stream(stream, device):
+    if stream is None:
+        return torch.cuda.current_stream(device)
+    if isinstance(stream, int):
+        return torch.cuda.ExternalStream(stream, device=device)
+    return stream
+
+
+def _ws(workspace, nbytes, device, stream=None):
+    device = torch.device(device)
+    s = _torch_stream(stream, device) if device.type == "cuda" else None
     if workspace is None:
-        workspace = _default_ws.setdefault(str(device), Workspace(device))
-    return workspace.get(nbytes)
+        key = (str(device), s.cuda_stream if s is not None else stream)
+        workspace = _default_ws.setdefault(key, Workspace(device))
+    buf = workspace if isinstance(workspace, torch.Tensor) else workspace.get(nbytes)
+    if isinstance(workspace, torch.Tensor) and buf.numel() < nbytes:
+        raise ValueError(f"workspace of {buf.numel()} bytes is smaller than the {nbytes} needed")
+    if s is not None and s.cuda_stream != torch.cuda.current_stream(device).cuda_stream:
+        # the buffer is used on another stream than the one it was allocated
+        # on: the allocator must not hand it out again before that work ends
+        buf.record_stream(s)
+    return buf
 
 
 # ---- filter + project -------------------------------------------------------------
@@ -292,7 +316,7 @@ def lms_filter_project(cols, preds=(), keep=(), projs=(), out=None, d_count=None
     if d_count is None:
         d_count = torch.zeros(2, dtype=torch.int64, device=dev)
     need = _lib.lms_filter_project_workspace(n)
-    ws = _ws(workspace, need, dev)
+    ws = _ws(workspace, need, dev, stream)
     rc = _lib.lms_filter_project(ctypes.byref(b.batch), pa, npred, ka, len(keep), pr, nproj, ctypes.byref(ob.batch),
                                  d_count.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
     _check(rc)
@@ -355,10 +379,30 @@ def lms_window_agg(cols, key_col, window: Window, aggs, preds=(), projs=(), grou
     aa = (lms_agg * max(1, len(aggs)))(*[lms_agg(f, c) for f, c in aggs])
     w = window.c()
     need = _lib.lms_window_agg_workspace(ctypes.byref(b.batch), key_col, ctypes.byref(w), aa, len(aggs))
-    ws = _ws(workspace, need, dev)
+    ws = _ws(workspace, need, dev, stream)
     rc = _lib.lms_window_agg(ctypes.byref(b.batch), pa, npred, pr, nproj, key_col, ctypes.byref(w), aa, len(aggs),
                              ctypes.byref(groups.c), d_count.data_ptr(), ws.data_ptr(), ws.numel(),
                              _stream_handle(stream))
+    _check(rc)
+    return groups, d_count
+
+
+def lms_window_agg_emit(aggs, workspace, groups: Groups | None = None, cap: int | None = None, d_count=None,
+                        stream=None):
+    """Enqueues the re-emission of the groups of the last lms_window_agg call
+    that used ``workspace`` (a Workspace or the tensor it handed out); returns
+    (groups, d_count).  The input columns are not read."""
+    buf = workspace.buf if isinstance(workspace, Workspace) else workspace
+    dev = buf.device
+    aggs = list(aggs)
+    if groups is None:
+        if cap is None:
+            raise ValueError("give groups or cap")
+        groups = Groups(cap, aggs, dev)
+    if d_count is None:
+        d_count = torch.zeros(2, dtype=torch.int64, device=dev)
+    rc = _lib.lms_window_agg_emit(ctypes.byref(groups.c), len(aggs), d_count.data_ptr(), buf.data_ptr(), buf.numel(),
+                                  _stream_handle(stream))
     _check(rc)
     return groups, d_count
 
@@ -604,7 +648,7 @@ def lms_hash_join(table: JoinTable, probe_keys: torch.Tensor, cap: int | None = 
     if d_count is None:
         d_count = torch.zeros(2, dtype=torch.int64, device=dev)
     need = _lib.lms_hash_join_workspace(n)
-    ws = _ws(workspace, need, dev)
+    ws = _ws(workspace, need, dev, stream)
     rc = _lib.lms_hash_join(table.handle, ctypes.byref(b.batch), 0, out[0].data_ptr(), out[1].data_ptr(), cap,
                             d_count.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
     _check(rc)

@@ -3,8 +3,8 @@
 Integer results must be bit-exact; AVG within 1e-5 relative.  Sizes span
 several tiles, partitions and pieces with ragged tails; edge cases cover empty
 inputs, empty filters, hot keys, key values equal to the table's empty marker,
-LDS overflow of a partition, output capacity below the group count, and a key
-with more panes than one workgroup table holds.
+LDS overflow of a partition, output capacity below the group count, a key
+with more panes than one workgroup table holds, and a window spanning more.
 """
 import numpy as np
 import pytest
@@ -273,12 +273,49 @@ def test_window_agg_capacity_below_count():
         assert int(got["aggs"][0][r]) == int(exp["aggs"][0][i])
 
 
-def test_window_agg_key_with_too_many_panes_reports_capacity():
-    from paper_2111_04289_amd import lms
+def one_hot_key_cols(lms, n_panes, rows_per_pane, pane_ms, cold_keys=0, seed=0):
+    """One key with rows in n_panes consecutive panes (rows_per_pane each),
+    plus optional cold keys spread over the same span."""
+    rng = np.random.default_rng(seed)
+    ts = np.repeat(np.arange(n_panes, dtype=np.int64) * pane_ms, rows_per_pane)
+    ts += rng.integers(0, pane_ms, ts.size)
+    key = np.full(ts.size, 77, np.int64)
+    if cold_keys:
+        cts = rng.integers(0, n_panes * pane_ms, cold_keys, dtype=np.int64)
+        ts = np.concatenate([ts, cts])
+        key = np.concatenate([key, rng.integers(1000, 1000 + cold_keys // 3, cold_keys, dtype=np.int64)])
+    perm = rng.permutation(ts.size)
+    ts, key = ts[perm], key[perm]
+    val = rng.integers(-1000, 1000, ts.size, dtype=np.int32)
+    f = rng.standard_normal(ts.size).astype(np.float32)
+    return [ts, key, val, f]
+
+
+@pytest.mark.parametrize("length,slide,rows_per_pane,cold", [
+    (1, 0, 1, 0),          # tumbling 1 ms over 10 s: one pane per row, one key
+    (1, 0, 3, 5000),       # three rows per pane: a split (pieces + merge) partition
+    (50, 10, 1, 3000),     # sliding, window of 5 panes
+    (30, 20, 2, 0),        # sliding with slide of 2 panes (window anchors every other pane)
+])
+def test_window_agg_key_with_more_panes_than_a_table(lms, length, slide, rows_per_pane, cold):
+    """A key holding more panes than one workgroup table is aggregated over
+    ranges of its windows instead of failing."""
+    pane = int(np.gcd(length, slide)) if slide else length
+    n_panes = 10000
+    log(f"many panes len={length} slide={slide} rows/pane={rows_per_pane} cold={cold}")
+    assert n_panes > lms.pane_limit(len(AGGS5))
+    cols = one_hot_key_cols(lms, n_panes, rows_per_pane, pane, cold, seed=length + slide)
+    got, cnt, status = gpu_window_agg(cols, 1, 0, length, slide, 0, AGGS5)
+    assert status == 0
+    assert_window_equal(got, oracle.window_agg(cols, 1, 0, length, slide, 0, AGGS5), AGGS5, "many panes")
+
+
+def test_window_agg_window_spanning_more_panes_than_a_table_reports_capacity(lms):
     limit = lms.pane_limit(len(AGGS5))
     n = 4 * limit
     cols = [np.arange(n, dtype=np.int64), np.zeros(n, np.int64), np.ones(n, np.int32), np.zeros(n, np.float32)]
-    got, cnt, status = gpu_window_agg(cols, 1, 0, 1, 0, 0, AGGS5)  # tumbling 1 ms: one pane per row, one key
+    # one window of n ms sliding by 1 ms: every window of the key holds up to n non-empty panes
+    got, cnt, status = gpu_window_agg(cols, 1, 0, n, 1, 0, AGGS5, cap=1 << 16)
     assert status == lms.LMS_ECAPACITY
 
 

@@ -14,6 +14,10 @@ Functions take NumPy arrays in host memory and return NumPy arrays:
   assigned to each window it falls in (the Expand semantics), no panes.
 * :func:`window_group`    -- the same definition evaluated for one output group.
 * :func:`hash_join`       -- Table II Join (Hash), stream-static inner equi-join.
+* :func:`window_query`    -- Table III's query shapes: a composite group key
+  (LR2S), HAVING on an aggregate (LR2S), ORDER BY an aggregate (CM1).
+* :func:`window_self_join` -- Table III's LR1: the stream joined with the rows
+  of its own window on equal keys.
 * :mod:`oracle.plan`      -- MapDevice (Algorithm 2) with Eq. 7-9.
 """
 from __future__ import annotations
@@ -57,6 +61,8 @@ def _load():
         _lib.orc_window_agg.restype = ctypes.c_int64
         _lib.orc_window_group.restype = ctypes.c_int64
         _lib.orc_hash_join.restype = ctypes.c_int64
+        _lib.orc_window_agg_keys.restype = ctypes.c_int64
+        _lib.orc_window_self_join.restype = ctypes.c_int64
     return _lib
 
 
@@ -201,4 +207,85 @@ def hash_join(build_keys, build_payload, probe_keys):
             raise MemoryError("oracle hash_join ran out of memory")
         if m <= cap:
             return oi[:m].copy(), op[:m].copy()
+        cap = int(m)
+
+
+def _cmp(v, op, c):
+    return {LT: v < c, LE: v <= c, GT: v > c, GE: v >= c, EQ: v == c, NE: v != c}[op]
+
+
+def window_query(cols, key_cols, ts_col, length, slide=0, origin=0, aggs=((COUNT, 0),), preds=(), projs=(),
+                 having=None, order_by=None):
+    """Windowed group-by over the tuple of key columns ``key_cols`` (Table III
+    LR2S: GROUPBY (highway, direction, segment)), then
+
+    * ``having=(k, op, value)``: keep the groups whose aggregate k satisfies
+      ``aggs[k] op value`` (LR2S: HAVING avgSpeed < 40.0);
+    * ``order_by=(k, descending)``: rows of each window ordered by aggregate k
+      (ascending unless descending), ties by the key tuple (CM1: ORDERBY
+      SUM(cpu)); without it, rows are sorted by (window start, key tuple).
+
+    Returns dict(keys=[int64[G] per key column], wstart=int64[G], aggs=[...]).
+    """
+    lib = _load()
+    q = _Query(cols, preds, projs)
+    aggs = list(aggs)
+    key_cols = list(key_cols)
+    nk = len(key_cols)
+    kc = _i32s(key_cols)
+    afn = _i32s(a[0] for a in aggs)
+    acol = _i32s(a[1] for a in aggs)
+    cap = 1024
+    while True:
+        ok = np.zeros(max(1, nk) * cap, np.int64)
+        ow = np.zeros(cap, np.int64)
+        oi = np.zeros(max(1, len(aggs)) * cap, np.int64)
+        of = np.zeros(max(1, len(aggs)) * cap, np.float64)
+        g = lib.orc_window_agg_keys(*q.args(), *q.proj_args(), ctypes.c_int(nk), _ptr(kc), ctypes.c_int(ts_col),
+                                    ctypes.c_int64(length), ctypes.c_int64(slide), ctypes.c_int64(origin),
+                                    ctypes.c_int(len(aggs)), _ptr(afn), _ptr(acol), ctypes.c_int64(cap), _ptr(ok),
+                                    _ptr(ow), _ptr(oi), _ptr(of))
+        if g == -2:
+            raise ValueError("1 to 4 key columns")
+        if g < 0:
+            raise MemoryError("oracle window_query ran out of memory")
+        if g <= cap:
+            break
+        cap = int(g)
+    res = {"keys": [ok[j * cap:j * cap + g].copy() for j in range(nk)], "wstart": ow[:g].copy(),
+           "aggs": [of[k * cap:k * cap + g].copy() if fn == AVG else oi[k * cap:k * cap + g].copy()
+                    for k, (fn, _) in enumerate(aggs)]}
+    if having is not None:
+        k, op, value = having
+        keep = _cmp(res["aggs"][k], op, value)
+        res = {"keys": [a[keep] for a in res["keys"]], "wstart": res["wstart"][keep],
+               "aggs": [a[keep] for a in res["aggs"]]}
+    if order_by is not None:
+        k, desc = order_by
+        v = res["aggs"][k]
+        # a stable sort: window start first, then the aggregate, then the key tuple
+        order = np.lexsort(tuple(reversed(res["keys"])) + ((-v if desc else v), res["wstart"]))
+        res = {"keys": [a[order] for a in res["keys"]], "wstart": res["wstart"][order],
+               "aggs": [a[order] for a in res["aggs"]]}
+    return res
+
+
+def window_self_join(cols, key_col, ts_col, length, slide=0, origin=0, preds=()):
+    """Every (window start, l, a) with rows l and a both passing, both in the
+    window and of equal key (Table III LR1: A.vehicle == L.vehicle over A's
+    range/slide window), in (window start, l, a) order."""
+    lib = _load()
+    q = _Query(cols, preds, ())
+    cap = max(1024, q.n)
+    while True:
+        ow = np.zeros(cap, np.int64)
+        ol = np.zeros(cap, np.int64)
+        oa = np.zeros(cap, np.int64)
+        m = lib.orc_window_self_join(*q.args(), ctypes.c_int(key_col), ctypes.c_int(ts_col),
+                                     ctypes.c_int64(length), ctypes.c_int64(slide), ctypes.c_int64(origin),
+                                     ctypes.c_int64(cap), _ptr(ow), _ptr(ol), _ptr(oa))
+        if m < 0:
+            raise MemoryError("oracle window_self_join ran out of memory")
+        if m <= cap:
+            return ow[:m].copy(), ol[:m].copy(), oa[:m].copy()
         cap = int(m)

@@ -311,6 +311,216 @@ int64_t orc_window_group(int64_t n, int ncols, const void* const* cols, const in
   return cnt;
 }
 
+typedef struct {
+  int64_t l, a;
+} orc_brow_pair;
+
+static int pair_cmp(const void* x, const void* y) {
+  const orc_brow_pair* p = (const orc_brow_pair*)x;
+  const orc_brow_pair* q = (const orc_brow_pair*)y;
+  if (p->l != q->l) return p->l < q->l ? -1 : 1;
+  if (p->a != q->a) return p->a < q->a ? -1 : 1;
+  return 0;
+}
+
+/* ---- Windowed group-by over a composite key ------------------------------
+ * Table III's LR2S groups by (highway, direction, segment): the group key is
+ * the tuple of nkey integer columns.  Same definition as orc_window_agg with
+ * the tuple in place of the single key: every passing row joins each window
+ * holding its event time; groups are sorted by (window start, key tuple).
+ * out_keys holds key column j of group g at out_keys[j*cap + g]. */
+
+typedef struct {
+  int64_t wstart;
+  int64_t key[4];
+  int64_t row;
+} orc_tmember;
+
+static int g_tnkey; /* tuple width for tmember_cmp (the oracle is single-threaded) */
+
+static int tmember_cmp(const void* a, const void* b) {
+  const orc_tmember* x = (const orc_tmember*)a;
+  const orc_tmember* y = (const orc_tmember*)b;
+  if (x->wstart != y->wstart) return x->wstart < y->wstart ? -1 : 1;
+  for (int j = 0; j < g_tnkey; ++j)
+    if (x->key[j] != y->key[j]) return x->key[j] < y->key[j] ? -1 : 1;
+  if (x->row != y->row) return x->row < y->row ? -1 : 1;
+  return 0;
+}
+
+static int same_group(const orc_tmember* x, const orc_tmember* y, int nkey) {
+  if (x->wstart != y->wstart) return 0;
+  for (int j = 0; j < nkey; ++j)
+    if (x->key[j] != y->key[j]) return 0;
+  return 1;
+}
+
+int64_t orc_window_agg_keys(int64_t n, int ncols, const void* const* cols, const int* dt, int npred,
+                            const int* pcol, const int* pop, const int64_t* pival, const double* pfval, int nproj,
+                            const int* prsrc, const int64_t* prmul, const int64_t* pradd, int nkey,
+                            const int* key_cols, int ts_col, int64_t len, int64_t slide, int64_t origin, int nagg,
+                            const int* afn, const int* acol, int64_t cap, int64_t* out_keys, int64_t* out_ws,
+                            int64_t* out_i, double* out_f) {
+  orc_query q = {n, ncols, cols, dt, npred, pcol, pop, pival, pfval, nproj, prsrc, prmul, pradd};
+  if (nkey < 1 || nkey > 4) return -2;
+  int64_t S = slide == 0 ? len : slide;
+  int64_t per_row = len / S + 2;
+  int64_t* wbuf = (int64_t*)malloc((size_t)per_row * sizeof(int64_t));
+  if (!wbuf) return -1;
+  int64_t nm = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!passes(&q, i)) continue;
+    int64_t total;
+    windows_of(get_int(cols[ts_col], dt[ts_col], i), len, S, origin, wbuf, 0, &total);
+    nm += total;
+  }
+  orc_tmember* mem = (orc_tmember*)malloc((size_t)(nm > 0 ? nm : 1) * sizeof(orc_tmember));
+  if (!mem) {
+    free(wbuf);
+    return -1;
+  }
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!passes(&q, i)) continue;
+    int64_t total;
+    int64_t got = windows_of(get_int(cols[ts_col], dt[ts_col], i), len, S, origin, wbuf, per_row, &total);
+    for (int64_t w = 0; w < got; ++w) {
+      mem[m].wstart = wbuf[w];
+      for (int j = 0; j < 4; ++j) mem[m].key[j] = j < nkey ? get_int(cols[key_cols[j]], dt[key_cols[j]], i) : 0;
+      mem[m].row = i;
+      ++m;
+    }
+  }
+  free(wbuf);
+  g_tnkey = nkey;
+  qsort(mem, (size_t)nm, sizeof(orc_tmember), tmember_cmp);
+  int64_t g = 0;
+  for (int64_t a = 0; a < nm;) {
+    int64_t b = a;
+    while (b < nm && same_group(&mem[b], &mem[a], nkey)) ++b;
+    if (g < cap) {
+      for (int j = 0; j < nkey; ++j) out_keys[j * cap + g] = mem[a].key[j];
+      out_ws[g] = mem[a].wstart;
+      for (int k = 0; k < nagg; ++k) {
+        int c = acol[k];
+        int64_t cnt = b - a;
+        if (afn[k] == ORC_COUNT) {
+          out_i[k * cap + g] = cnt;
+        } else if (afn[k] == ORC_AVG) {
+          double s = 0.0;
+          for (int64_t r = a; r < b; ++r) s += ext_dbl(&q, c, mem[r].row);
+          out_f[k * cap + g] = s / (double)cnt;
+        } else {
+          uint64_t s = 0;
+          int64_t mn = ext_int(&q, c, mem[a].row), mx = mn;
+          for (int64_t r = a; r < b; ++r) {
+            int64_t v = ext_int(&q, c, mem[r].row);
+            s += (uint64_t)v;
+            if (v < mn) mn = v;
+            if (v > mx) mx = v;
+          }
+          out_i[k * cap + g] = afn[k] == ORC_SUM ? (int64_t)s : (afn[k] == ORC_MIN ? mn : mx);
+        }
+      }
+    }
+    ++g;
+    a = b;
+  }
+  free(mem);
+  return g;
+}
+
+/* ---- Windowed self-join ---------------------------------------------------
+ * Table III's LR1 joins the stream with the rows of its own range/slide window
+ * on equal keys (A.vehicle == L.vehicle).  Read per micro-batch: for every
+ * window and every ordered pair of passing rows (l, a) that both lie in the
+ * window and have equal keys (l == a included), one output (window start, l,
+ * a).  Listed in (window start, l, a) order.  Writes min(pairs, cap); returns
+ * the number of pairs, or -1 if memory ran out. */
+int64_t orc_window_self_join(int64_t n, int ncols, const void* const* cols, const int* dt, int npred,
+                             const int* pcol, const int* pop, const int64_t* pival, const double* pfval,
+                             int key_col, int ts_col, int64_t len, int64_t slide, int64_t origin, int64_t cap,
+                             int64_t* out_ws, int64_t* out_l, int64_t* out_a) {
+  orc_query q = {n, ncols, cols, dt, npred, pcol, pop, pival, pfval, 0, NULL, NULL, NULL};
+  int64_t S = slide == 0 ? len : slide;
+  int64_t per_row = len / S + 2;
+  int64_t* wbuf = (int64_t*)malloc((size_t)per_row * sizeof(int64_t));
+  if (!wbuf) return -1;
+  int64_t nm = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!passes(&q, i)) continue;
+    int64_t total;
+    windows_of(get_int(cols[ts_col], dt[ts_col], i), len, S, origin, wbuf, 0, &total);
+    nm += total;
+  }
+  orc_member* mem = (orc_member*)malloc((size_t)(nm > 0 ? nm : 1) * sizeof(orc_member));
+  if (!mem) {
+    free(wbuf);
+    return -1;
+  }
+  int64_t m = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!passes(&q, i)) continue;
+    int64_t total;
+    int64_t got = windows_of(get_int(cols[ts_col], dt[ts_col], i), len, S, origin, wbuf, per_row, &total);
+    for (int64_t w = 0; w < got; ++w) {
+      mem[m].wstart = wbuf[w];
+      mem[m].key = get_int(cols[key_col], dt[key_col], i);
+      mem[m].row = i;
+      ++m;
+    }
+  }
+  free(wbuf);
+  /* members sorted by (window, key, row): each run of equal (window, key) is a
+   * window's rows of one key in row order, and its pairs are the run squared.
+   * A window's pairs are collected, then sorted into (l, a) order. */
+  qsort(mem, (size_t)nm, sizeof(orc_member), member_cmp);
+  int64_t g = 0;
+  int64_t pcap = 1024;
+  orc_brow_pair* pairs = (orc_brow_pair*)malloc((size_t)pcap * sizeof(orc_brow_pair));
+  if (!pairs) {
+    free(mem);
+    return -1;
+  }
+  for (int64_t a = 0; a < nm;) {
+    int64_t wend = a;
+    while (wend < nm && mem[wend].wstart == mem[a].wstart) ++wend;
+    int64_t c = 0;
+    for (int64_t r = a; r < wend;) {
+      int64_t e = r;
+      while (e < wend && mem[e].key == mem[r].key) ++e;
+      for (int64_t x = r; x < e; ++x)
+        for (int64_t y = r; y < e; ++y) {
+          if (c == pcap) {
+            orc_brow_pair* grown = (orc_brow_pair*)realloc(pairs, (size_t)(2 * pcap) * sizeof(orc_brow_pair));
+            if (!grown) {
+              free(pairs);
+              free(mem);
+              return -1;
+            }
+            pairs = grown;
+            pcap *= 2;
+          }
+          pairs[c].l = mem[x].row;
+          pairs[c].a = mem[y].row;
+          ++c;
+        }
+      r = e;
+    }
+    qsort(pairs, (size_t)c, sizeof(orc_brow_pair), pair_cmp);
+    for (int64_t k = 0; k < c; ++k, ++g)
+      if (g < cap) {
+        out_ws[g] = mem[a].wstart;
+        out_l[g] = pairs[k].l;
+        out_a[g] = pairs[k].a;
+      }
+    a = wend;
+  }
+  free(pairs);
+  free(mem);
+  return g;
+}
+
 /* ---- Stream-static join ------------------------------------------------- */
 
 typedef struct {

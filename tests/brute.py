@@ -95,3 +95,59 @@ def hash_join(build_keys, build_payload, probe_keys):
             if bk == k:
                 out.append((i, build_payload[j]))
     return out
+
+
+def window_query(cols, key_cols, ts_col, length, slide, origin, aggs, preds=(), projs=(), bits=None):
+    """Dict (wstart, key tuple) -> aggregate values, by looping over every
+    candidate window start, every key tuple and every row."""
+    n = len(cols[0])
+    bits = bits or [32] * len(cols)
+    S = slide or length
+    if n == 0:
+        return {}
+    tmin, tmax = min(cols[ts_col]), max(cols[ts_col])
+    kmin = (tmin - origin - length) // S - 1
+    kmax = (tmax - origin) // S + 1
+    tuples = sorted({tuple(cols[c][i] for c in key_cols) for i in range(n)})
+    res = {}
+    for k in range(kmin, kmax + 1):
+        s = origin + k * S
+        for t in tuples:
+            rows = [i for i in range(n)
+                    if tuple(cols[c][i] for c in key_cols) == t and s <= cols[ts_col][i] < s + length
+                    and passes(cols, preds, i)]
+            if not rows:
+                continue
+            vals = []
+            for fn, c in aggs:
+                xs = [row_value(cols, c, i, projs, bits) for i in rows]
+                if fn == COUNT:
+                    vals.append(len(rows))
+                elif fn == SUM:
+                    vals.append(_wrap(sum(int(x) for x in xs), 64))
+                elif fn == MIN:
+                    vals.append(min(xs))
+                elif fn == MAX:
+                    vals.append(max(xs))
+                else:
+                    vals.append(math.fsum(float(x) for x in xs) / len(rows))
+            res[(s, t)] = vals
+    return res
+
+
+def window_self_join(cols, key_col, ts_col, length, slide, origin, preds=()):
+    """List of (wstart, l, a) by looping over window starts and all row pairs."""
+    n = len(cols[0])
+    S = slide or length
+    if n == 0:
+        return []
+    tmin, tmax = min(cols[ts_col]), max(cols[ts_col])
+    out = []
+    for k in range((tmin - origin - length) // S - 1, (tmax - origin) // S + 2):
+        s = origin + k * S
+        for l in range(n):
+            for a in range(n):
+                if (cols[key_col][l] == cols[key_col][a] and s <= cols[ts_col][l] < s + length
+                        and s <= cols[ts_col][a] < s + length and passes(cols, preds, l) and passes(cols, preds, a)):
+                    out.append((s, l, a))
+    return out

@@ -14,6 +14,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_query_pins as qpins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "lms_oracle.c")
 
@@ -29,6 +30,12 @@ MUTANTS = {
     "runs_ignore_key": ("mem[b].wstart == mem[a].wstart && mem[b].key == mem[a].key",
                         "mem[b].wstart == mem[a].wstart"),
     "sum_of_first_row": ("s += (uint64_t)v;", "s = (uint64_t)v;"),
+    "tuple_ignores_last_key": ("if (x->key[j] != y->key[j]) return 0;",
+                               "if (j + 1 < nkey && x->key[j] != y->key[j]) return 0;"),
+    "tuple_keys_unsorted": ("if (x->key[j] != y->key[j]) return x->key[j] < y->key[j] ? -1 : 1;", ""),
+    "self_join_ordered_pairs_only": ("for (int64_t y = r; y < e; ++y) {", "for (int64_t y = x; y < e; ++y) {"),
+    "self_join_runs_ignore_key": ("while (e < wend && mem[e].key == mem[r].key) ++e;\n      for (int64_t x",
+                                  "while (e < wend) ++e;\n      for (int64_t x"),
 }
 
 
@@ -46,6 +53,10 @@ def battery():
         lambda: pins.test_sliding_equals_merge_of_tumbling_panes(10, 2, 3),
         *[(lambda s=s: pins.test_join_matches_brute_force(s)) for s in range(8)],
         pins.test_join_pandas_merge_and_unique_keys,
+        *[(lambda s=s: qpins.test_composite_key_query_matches_brute_force(s)) for s in range(8)],
+        qpins.test_composite_key_equals_single_key_on_tuple_ids,
+        *[(lambda s=s: qpins.test_self_join_matches_brute_force(s)) for s in range(6)],
+        qpins.test_self_join_counts_are_squares_of_window_counts,
     ]
     for c in checks:
         try:
@@ -65,7 +76,8 @@ def test_pins_reject_planted_mistake(name, tmp_path):
     lib_path = tmp_path / "libmut.so"
     subprocess.check_call(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", "-o", str(lib_path), str(src)])
     lib = ctypes.CDLL(str(lib_path))
-    for fn in ("orc_filter_project", "orc_window_agg", "orc_window_group", "orc_hash_join"):
+    for fn in ("orc_filter_project", "orc_window_agg", "orc_window_group", "orc_hash_join", "orc_window_agg_keys",
+               "orc_window_self_join"):
         getattr(lib, fn).restype = ctypes.c_int64
     saved = oracle._load()
     oracle._lib = lib

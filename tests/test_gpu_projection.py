@@ -97,14 +97,16 @@ def test_filter_project_int32_wrap(lms):
 @pytest.mark.parametrize("length,slide", [(1000, 0), (3000, 1000)])
 def test_window_agg_over_wrapping_projection(lms, length, slide):
     cols = wrap_cols(2, 300000)
-    preds = [(2, GE, (1 << 30) + (1 << 29))]
+    # 3 * val modulo 2^32 is negative for val in [1.25, 4/3) * 2^30 and
+    # positive above, so both signs of wrapped value reach the aggregates
+    preds = [(2, GE, (1 << 30) + (1 << 28))]
     projs = [(2, 3, 0)]
     aggs = [(COUNT, 0), (SUM, 4), (MIN, 4), (MAX, 4)]
     got, cnt, status = gpu_window_agg(cols, 1, 0, length, slide, 0, aggs, preds, projs)
     assert status == 0
     exp = oracle.window_agg(cols, 1, 0, length, slide, 0, aggs, preds, projs)
     assert_window_equal(got, exp, aggs, "wrap")
-    assert (exp["aggs"][2] < 0).any()  # wrapped values reached the aggregates
+    assert (exp["aggs"][2] < 0).any() and (exp["aggs"][3] > 0).any()  # both signs wrapped
     log("multi-batch form of the same query")
     batches = [wrap_cols(10 + i, n) for i, n in enumerate([1000, 77777, 5, 150000])]
     w = lms.Window(0, length, slide, 0)

@@ -158,6 +158,23 @@ int lms_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred
                        int32_t nkeep, const lms_proj* projs, int32_t nproj, const lms_batch* out,
                        int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream);
 
+/* Allocation-free variant of lms_filter_project, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, semantics and results as
+ * lms_filter_project, without the workspace: its per-tile counts live in a
+ * fixed 1 MiB array in the library's device memory, one per GPU, held until
+ * the process ends.  in->nrows must not exceed
+ * lms_filter_project_noalloc_max_rows() (2^28), else LMS_EINVAL.  The first
+ * call on a device looks up that device's copy of the array (a host-side
+ * HIP query; it may fail with LMS_EHIP); no call allocates.  Every call on a
+ * GPU shares that GPU's array, so calls that overlap in time on one GPU (on
+ * different streams, or from different threads) race and give wrong results:
+ * order them on one stream or by events. */
+int64_t lms_filter_project_noalloc_max_rows(void);
+int lms_filter_project_noalloc(const lms_batch* in, const lms_pred* preds, int32_t npred, const int32_t* keep,
+                               int32_t nkeep, const lms_proj* projs, int32_t nproj, const lms_batch* out,
+                               int64_t* d_count, lms_stream stream);
+
 /* ---- Windowed hash group-by (Table II "Aggregation (Hash)" and "Expand";
  * windows per Table I SlideTime and the range/slide clauses of Table III) ---
  * Groups the rows that pass the predicates by (cols[key_col], window) and

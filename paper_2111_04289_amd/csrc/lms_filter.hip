@@ -7,6 +7,7 @@
 // without any global atomic or workgroup barrier, and both the column loads
 // and the output writes are contiguous per wave.
 #include <algorithm>
+#include <mutex>
 
 #include "lms_internal.h"
 
@@ -275,9 +276,15 @@ extern "C" size_t lms_filter_project_workspace(int64_t nrows) {
   return nrows < 0 ? 0 : fp_workspace(nrows, nullptr, nullptr);
 }
 
-extern "C" int lms_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred, const int32_t* keep,
-                                  int32_t nkeep, const lms_proj* projs, int32_t nproj, const lms_batch* out,
-                                  int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream) {
+namespace lms {
+namespace {
+
+// Validates the call and enqueues the three launches.  `workspace` is either
+// the caller's buffer or the device address of the fixed scratch array;
+// ws_bytes is its size in both cases.
+int fp_run(const lms_batch* in, const lms_pred* preds, int32_t npred, const int32_t* keep, int32_t nkeep,
+           const lms_proj* projs, int32_t nproj, const lms_batch* out, int64_t* d_count, void* workspace,
+           size_t ws_bytes, lms_stream stream) {
   FpArgs a{};
   int rc = build_query(in, preds, npred, projs, nproj, &a.q);
   if (rc) return rc;
@@ -326,4 +333,59 @@ extern "C" int lms_filter_project(const lms_batch* in, const lms_pred* preds, in
     LMS_LAUNCH("k_fp_write", k_fp_write, dim3(wgs), dim3(kTPB), 0, st, a);
   }
   return check_hip(hipGetLastError(), "filter_project launch");
+}
+
+// Fixed scratch of the allocation-free entry point: the tile counts and tile
+// offsets of up to kScratchTiles wave tiles (1 MiB per device, held until the
+// process ends).  Host code never passes `scratch` itself to a kernel (in host
+// code the name is a stand-in, not a device address); it uses the address
+// hipGetSymbolAddress returned for the current device.
+constexpr int64_t kScratchTiles = 65536;
+constexpr int64_t kScratchRows = kScratchTiles * kWaveRows;  // 2^28
+__device__ __align__(256) int64_t scratch[2 * kScratchTiles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+int scratch_address(void** out) {
+  int dev = -1;
+  int rc = check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return set_error(LMS_EINVAL, "device %d beyond the %d supported", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    rc = check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc) return rc;
+    if (!p) return set_error(LMS_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LMS_OK;
+}
+
+}  // namespace
+}  // namespace lms
+
+extern "C" int lms_filter_project(const lms_batch* in, const lms_pred* preds, int32_t npred, const int32_t* keep,
+                                  int32_t nkeep, const lms_proj* projs, int32_t nproj, const lms_batch* out,
+                                  int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream) {
+  return fp_run(in, preds, npred, keep, nkeep, projs, nproj, out, d_count, workspace, ws_bytes, stream);
+}
+
+extern "C" int64_t lms_filter_project_noalloc_max_rows(void) { return kScratchRows; }
+
+extern "C" int lms_filter_project_noalloc(const lms_batch* in, const lms_pred* preds, int32_t npred,
+                                          const int32_t* keep, int32_t nkeep, const lms_proj* projs, int32_t nproj,
+                                          const lms_batch* out, int64_t* d_count, lms_stream stream) {
+  if (!in) return set_error(LMS_EINVAL, "input batch is NULL");
+  if (in->nrows > kScratchRows)
+    return set_error(LMS_EINVAL, "%lld rows exceed the %lld the fixed scratch of lms_filter_project_noalloc covers",
+                     (long long)in->nrows, (long long)kScratchRows);
+  void* ws = nullptr;
+  int rc = scratch_address(&ws);
+  if (rc) return rc;
+  return fp_run(in, preds, npred, keep, nkeep, projs, nproj, out, d_count, ws, sizeof(int64_t) * 2 * kScratchTiles,
+                stream);
 }

@@ -136,6 +136,9 @@ _SIGS = {
     "lms_filter_project_workspace": (_sz, [_i64]),
     "lms_filter_project": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(ctypes.c_int32), _i32, _P(lms_proj),
                                           _i32, _P(lms_batch), _vp, _vp, _sz, _vp]),
+    "lms_filter_project_noalloc_max_rows": (_i64, []),
+    "lms_filter_project_noalloc": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(ctypes.c_int32), _i32,
+                                                  _P(lms_proj), _i32, _P(lms_batch), _vp, _vp]),
     "lms_window_agg_workspace": (_sz, [_P(lms_batch), _i32, _P(lms_window), _P(lms_agg), _i32]),
     "lms_window_agg_pane_limit": (_i64, [_i32]),
     "lms_window_agg": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _i32, _P(lms_window),
@@ -319,6 +322,24 @@ def lms_filter_project(cols, preds=(), keep=(), projs=(), out=None, d_count=None
     ws = _ws(workspace, need, dev, stream)
     rc = _lib.lms_filter_project(ctypes.byref(b.batch), pa, npred, ka, len(keep), pr, nproj, ctypes.byref(ob.batch),
                                  d_count.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    _check(rc)
+    return out, d_count
+
+
+def lms_filter_project_noalloc(cols, out, d_count, preds=(), keep=(), projs=(), stream=None):
+    """Enqueues filter+project with the library's fixed scratch (no workspace).
+
+    The caller supplies the output columns (room for every input row) and the
+    device int64[2] count; calls that overlap on one GPU race (lms.h)."""
+    b = _Batch(cols)
+    keep = list(keep)
+    projs = list(projs)
+    ob = _Batch(out, nrows=b.batch.nrows)
+    pa, npred = _preds(preds)
+    pr, nproj = _projs(projs)
+    ka = (ctypes.c_int32 * max(1, len(keep)))(*keep)
+    rc = _lib.lms_filter_project_noalloc(ctypes.byref(b.batch), pa, npred, ka, len(keep), pr, nproj,
+                                         ctypes.byref(ob.batch), d_count.data_ptr(), _stream_handle(stream))
     _check(rc)
     return out, d_count
 

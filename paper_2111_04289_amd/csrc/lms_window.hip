@@ -601,7 +601,7 @@ struct Lds {
 
 enum { M_OVF = 0, M_SSIZE = 1, M_PC = 2, M_BASE_LO = 3, M_BASE_HI = 4, M_QMIN = 5, M_QMAX = 6, M_PLO = 7, M_PHI = 8,
        // sliding emission: output pointers (okey, ows, oagg[]) and per-aggregate codes
-       M_OUT = 16, M_CODE = M_OUT + 2 * (2 + kMaxAggs), M_WORDS = M_CODE + kMaxAggs };
+       M_OUT = 16, M_CODE = M_OUT + 2 * (2 + kMaxAggs), M_ACCFN = M_CODE + kMaxAggs, M_WORDS = M_ACCFN + kMaxAggs };
 
 __host__ __device__ inline size_t lds_bytes(int ek, int eg, int nacc) {
   size_t b = 0;
@@ -747,6 +747,18 @@ __device__ __forceinline__ void finish_row(const WinArgs& a, Elem<MA>& x) {
   }
 }
 
+// Marks every field of x as redefined here (an empty asm taking each one):
+// the compiler's wait-count tracking then no longer ties these registers to
+// the loads that filled them, so a later use does not wait for loads issued
+// after this point (without it, the first use after the next round's loads
+// waited for all of them).
+template <int MA>
+__device__ __forceinline__ void settle(Elem<MA>& x) {
+  asm volatile("" : "+v"(x.key), "+v"(x.pane), "+v"(x.cnt));
+#pragma unroll
+  for (int k = 0; k < MA; ++k) asm volatile("" : "+v"(x.in[k]));
+}
+
 template <int MA>
 __device__ __forceinline__ void load_partial(const WinArgs& a, uint32_t e, Elem<MA>& x) {
   x.key = a.pkey[e];
@@ -868,6 +880,7 @@ __device__ __forceinline__ void fill_out_table(const WinArgs& a, Lds& s) {
     for (int k = 0; k < kMaxAggs; ++k) {
       out[2 + k] = (uint64_t)a.oagg[k];
       s.misc[M_CODE + k] = ((uint32_t)a.afn[k] & 0xffu) | (((uint32_t)a.aacc[k] & 0xffu) << 8);
+      s.misc[M_ACCFN + k] = (uint32_t)a.accfn[k];
     }
   }
 }
@@ -949,64 +962,81 @@ __device__ __forceinline__ int64_t fdiv(int64_t x, int64_t d, double inv) {
   return q;
 }
 
+// Accumulator slot A (an eg-strided LDS array) combined over entries
+// [i, hi) of a key's pane-sorted run.  fn is uniform across the wave, so the
+// switch is taken once per slot and each case is a plain loop.
+__device__ __forceinline__ uint64_t combine_run(int fn, const uint64_t* A, uint32_t i, uint32_t hi) {
+  uint64_t x = A[i];
+  switch (fn) {
+    case LMS_SUM:
+      for (uint32_t j = i + 1; j < hi; ++j) x += A[j];
+      return x;
+    case LMS_MIN:
+      for (uint32_t j = i + 1; j < hi; ++j) x = (int64_t)A[j] < (int64_t)x ? A[j] : x;
+      return x;
+    case LMS_MAX:
+      for (uint32_t j = i + 1; j < hi; ++j) x = (int64_t)A[j] > (int64_t)x ? A[j] : x;
+      return x;
+    default: {
+      double d = __longlong_as_double((long long)x);
+      for (uint32_t j = i + 1; j < hi; ++j) d += __longlong_as_double((long long)A[j]);
+      return (uint64_t)__double_as_longlong(d);
+    }
+  }
+}
+
 // One output row of the sliding composition: row r, owned by sorted entry i.
+// The window's panes are the key's entries [i, hi): entry i (the first pane
+// the window holds) and the following ones whose first window is not after
+// w; first windows are nondecreasing along a key's run, so they form a
+// prefix, found four entries per step.  Each accumulator is then combined
+// over [i, hi) under the uniform function of its slot (fnk[k]), in entry
+// order (so double sums are added in pane order).
 template <int MA>
 __device__ __forceinline__ void emit_row(const WinArgs& a, Lds& s, uint32_t i, uint32_t r, int64_t base,
-                                         int64_t wbase) {
-  {
-    const int64_t idx = base + r;
-    if (idx >= a.cap) return;
-    const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
-    const uint64_t kk = s.sorted[i];
-    const uint32_t kid = (uint32_t)kk, ke = (uint32_t)(kk >> 32);
-    // the window's panes are the key's entries from i on whose first window is
-    // not after w.  Entry i is always one of them (its first window is not
-    // after the first window it owns), so the accumulators start from its
-    // values rather than from the identities (a pane's own double sum is never
-    // -0.0, so the sums keep their bits).
-    uint32_t cnt = s.gcnt[i];
-    uint64_t acc[MA];
+                                         int64_t wbase, const int (&fnk)[MA]) {
+  const int64_t idx = base + r;
+  if (idx >= a.cap) return;
+  const int32_t w = s.wlo[i] + (int32_t)(r - s.order[i]);
+  const uint64_t kk = s.sorted[i];
+  const uint32_t kid = (uint32_t)kk, ke = (uint32_t)(kk >> 32);
+  const uint32_t last = (uint32_t)a.eg - 1;
+  uint32_t hi = i + 1;
+  while (true) {
+    int32_t f[4];
 #pragma unroll
-    for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? s.acc[(size_t)k * a.eg + i] : 0;
-    // four entries are loaded per step, so the LDS round trips of a step
-    // overlap instead of each waiting on the previous test
-    constexpr int kStep = MA <= 2 ? 4 : MA <= 4 ? 2 : 1;  // wider unrolls would spill
-    for (uint32_t j = i + 1; j < ke; j += kStep) {
-      bool more = true;
+    for (int u = 0; u < 4; ++u) f[u] = s.fw[min(hi + u, last)];  // in bounds, issued together
+    uint32_t c = 0;
 #pragma unroll
-      for (int u = 0; u < kStep; ++u) {
-        const uint32_t jj = j + u;
-        const bool ok = jj < ke;
-        const bool in = ok && s.fw[jj] <= w;
-        cnt += in ? s.gcnt[jj] : 0u;
+    for (int u = 0; u < 4; ++u) c += (hi + u < ke && f[u] <= w) ? 1u : 0u;
+    hi += c;
+    if (c < 4) break;
+  }
+  uint32_t cnt = s.gcnt[i];
+  for (uint32_t j = i + 1; j < hi; ++j) cnt += s.gcnt[j];
+  uint64_t acc[MA];
 #pragma unroll
-        for (int k = 0; k < MA; ++k)
-          if (k < a.nacc && in) acc[k] = combine(a.accfn[k], acc[k], s.acc[(size_t)k * a.eg + jj]);
-        more = in;
-      }
-      if (!more) break;
-    }
-    // output pointers and aggregate codes: the table of fill_out_table
-    const uint64_t* const out = (const uint64_t*)(s.misc + M_OUT);
-    const uint32_t* const code = s.misc + M_CODE;
-    out_store((int64_t*)out[0] + idx, key_of(a, s, kid));
-    out_store((int64_t*)out[1] + idx, a.origin + ((int64_t)w + wbase) * a.slide);
+  for (int k = 0; k < MA; ++k) acc[k] = k < a.nacc ? combine_run(fnk[k], s.acc + (size_t)k * a.eg, i, hi) : 0;
+  // output pointers and aggregate codes: the table of fill_out_table
+  const uint64_t* const out = (const uint64_t*)(s.misc + M_OUT);
+  const uint32_t* const code = s.misc + M_CODE;
+  out_store((int64_t*)out[0] + idx, key_of(a, s, kid));
+  out_store((int64_t*)out[1] + idx, a.origin + ((int64_t)w + wbase) * a.slide);
 #pragma unroll
-    for (int k = 0; k < kMaxAggs; ++k) {
-      if (k >= a.nagg) break;
-      const uint32_t c = code[k];
-      const int fn = (int)(c & 0xffu);
-      void* const op = (void*)out[2 + k];
-      if (fn == LMS_COUNT) {
-        out_store((int64_t*)op + idx, (int64_t)cnt);
-      } else {
-        const int slot = (int)(c >> 8);
-        uint64_t x = acc[0];
+  for (int k = 0; k < kMaxAggs; ++k) {
+    if (k >= a.nagg) break;
+    const uint32_t c = code[k];
+    const int fn = (int)(c & 0xffu);
+    void* const op = (void*)out[2 + k];
+    if (fn == LMS_COUNT) {
+      out_store((int64_t*)op + idx, (int64_t)cnt);
+    } else {
+      const int slot = (int)(c >> 8);
+      uint64_t x = acc[0];
 #pragma unroll
-        for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
-        if (fn == LMS_AVG) out_store((double*)op + idx, __longlong_as_double((long long)x) / (double)cnt);
-        else out_store((int64_t*)op + idx, (int64_t)x);
-      }
+      for (int j = 1; j < MA; ++j) x = slot == j ? acc[j] : x;
+      if (fn == LMS_AVG) out_store((double*)op + idx, __longlong_as_double((long long)x) / (double)cnt);
+      else out_store((int64_t*)op + idx, (int64_t)x);
     }
   }
 }
@@ -1161,12 +1191,15 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0, int64_t wmin,
   }
   const int64_t base = reserve_output(a, s, total);  // its barrier publishes the map
   const int64_t wbase = b0 / a.R;
+  int fnk[MA];  // accumulator functions, uniform: read once
+#pragma unroll
+  for (int k = 0; k < MA; ++k) fnk[k] = __builtin_amdgcn_readfirstlane((int)s.misc[M_ACCFN + k]);
   // Rows go out in blocks of 64, one per lane, each wave taking every
   // (kAggTPB / 64)-th block.  Nothing here needs a workgroup barrier, so a
   // wave's output stores overlap its next block instead of being waited for.
   const uint32_t lane = threadIdx.x & 63;
   if (mapped) {
-    for (uint32_t r = threadIdx.x; r < total; r += kAggTPB) emit_row<MA>(a, s, rmap[r], r, base, wbase);
+    for (uint32_t r = threadIdx.x; r < total; r += kAggTPB) emit_row<MA>(a, s, rmap[r], r, base, wbase, fnk);
     return;
   }
   // Without the map, lane 0 finds the block's first entry and broadcasts it;
@@ -1193,7 +1226,7 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0, int64_t wmin,
         if (s.order[mid] <= r) lo = mid;
         else hi = mid - 1;
       }
-      emit_row<MA>(a, s, lo, r, base, wbase);
+      emit_row<MA>(a, s, lo, r, base, wbase, fnk);
     }
   }
 }
@@ -1257,20 +1290,26 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg,
       }
       for (uint32_t b = lo; b < hi; b += kAggTPB) {
         const uint32_t e = b + threadIdx.x;
-        Elem<MA> nxt;  // the next round's element is loaded while this round inserts
+        // This round's element is converted before the next round's loads are
+        // issued, and inserted while they are in flight: a conversion after
+        // them waits on every outstanding load (the wait counter is in issue
+        // order), which would leave no load in flight during the insertion.
+        bool ins = false;
+        uint64_t h = 0;
+        if (e < hi) {
+          if (!sg.partial) finish_row<MA>(a, cur);
+          h = fmix64((uint64_t)cur.key);
+          const uint32_t sh = subhash(h);
+          const int64_t q = (int64_t)cur.pane;
+          ins = sh >= rlo && sh < rhi && q >= ilo && q < ihi;
+        }
+        settle<MA>(cur);  // on every path, so no path reaches the insertion with a pending load
+        Elem<MA> nxt;
         if (e + kAggTPB < hi) {
           if (sg.partial) load_partial<MA>(a, e + kAggTPB, nxt);
           else load_row<MA>(a, e + kAggTPB, nxt);
         }
-        if (e < hi) {
-          if (!sg.partial) finish_row<MA>(a, cur);
-          const uint64_t h = fmix64((uint64_t)cur.key);
-          const uint32_t sh = subhash(h);
-          const int64_t q = (int64_t)cur.pane;
-          if (sh >= rlo && sh < rhi && q >= ilo && q < ihi) {
-            if (!insert<MA>(a, s, cur, h)) s.misc[M_OVF] = 1;
-          }
-        }
+        if (ins && !insert<MA>(a, s, cur, h)) s.misc[M_OVF] = 1;
         cur = nxt;
         __syncthreads();
         const bool o = s.misc[M_OVF] != 0;
@@ -1406,11 +1445,14 @@ __device__ void aggregate_piece(const WinArgs& a, Lds& s, const Item& it) {
     const uint32_t e = b + threadIdx.x;
     bool pending = false;
     Elem<MA> x = nxt;
-    if (e + kAggTPB < it.hi) load_row<MA>(a, e + kAggTPB, nxt);  // prefetch the next round
     uint64_t h = 0;
-    if (e < it.hi) {
+    if (e < it.hi) {  // converted before the next round's loads are issued (see aggregate_and_emit)
       finish_row<MA>(a, x);
       h = fmix64((uint64_t)x.key);
+    }
+    settle<MA>(x);
+    if (e + kAggTPB < it.hi) load_row<MA>(a, e + kAggTPB, nxt);  // prefetch the next round
+    if (e < it.hi) {
       if (!insert<MA>(a, s, x, h)) {
         pending = true;
         s.misc[M_OVF] = 1;

@@ -218,6 +218,67 @@ int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_t npred, co
 int lms_window_agg_emit(const lms_groups* out, int32_t nagg, int64_t* d_count, void* workspace, size_t ws_bytes,
                         lms_stream stream);
 
+/* ---- Table III query shapes: composite keys, HAVING, ORDER BY ------------------
+ * The windowed group-by of lms_window_agg with
+ *  - a composite group key: the tuple of nkey integer columns (LR2S groups by
+ *    highway, direction and segment).  For nkey > 1 each part declares the
+ *    value domain [lo, hi] of its column (a schema property: every passing
+ *    row's value must lie in it, else d_count[1] = LMS_ERANGE); the domains'
+ *    product must not exceed 2^62 tuples.  For nkey == 1, lo and hi are
+ *    ignored;
+ *  - HAVING (optional): only groups with aggs[having->agg] op value are kept
+ *    (ival for integer aggregates, fval for AVG; LR2S keeps avgSpeed < 40);
+ *  - ORDER BY (optional; Table II "Sorting", CM1 orders by SUM(cpu)): rows
+ *    ordered by window start, then by aggs[order->agg] (descending if asked),
+ *    then by the key tuple; without it, row order is unspecified.
+ * Output: out->keys[j] (int64, the key part widened), out->wstart, out->aggs
+ * as in lms_groups, capacity out->cap.  out->cap must hold every (key tuple,
+ * window) group before HAVING: else d_count[1] = LMS_ECAPACITY and nothing
+ * is valid.  d_count[0] = rows written (after HAVING).
+ * Workspace: lms_window_query_workspace() with the same key parts, window,
+ * aggregates, whether ORDER BY is given, and the capacity. */
+typedef struct {
+  int32_t col;
+  int32_t reserved;
+  int64_t lo, hi; /* value domain of the key column (nkey > 1) */
+} lms_keypart;
+typedef struct {
+  int32_t agg; /* index into aggs */
+  int32_t op;  /* lms_cmp */
+  int64_t ival;
+  double fval;
+} lms_having;
+typedef struct {
+  int32_t agg;
+  int32_t descending;
+} lms_order;
+typedef struct {
+  int64_t* const* keys; /* host array of nkey device columns */
+  int64_t* wstart;
+  void* const* aggs;
+  int64_t cap;
+} lms_qgroups;
+size_t lms_window_query_workspace(const lms_batch* in, const lms_keypart* keys, int32_t nkey, const lms_window* w,
+                                  const lms_agg* aggs, int32_t nagg, int32_t ordered, int64_t cap);
+int lms_window_query(const lms_batch* in, const lms_pred* preds, int32_t npred, const lms_proj* projs, int32_t nproj,
+                     const lms_keypart* keys, int32_t nkey, const lms_window* w, const lms_agg* aggs, int32_t nagg,
+                     const lms_having* having, const lms_order* order, const lms_qgroups* out, int64_t* d_count,
+                     void* workspace, size_t ws_bytes, lms_stream stream);
+
+/* ---- Windowed self-join (Table III LR1: the stream joined with the rows of
+ * its own range/slide window on equal keys, A.vehicle == L.vehicle) ---------
+ * For every window and every ordered pair (l, a) of rows that both pass the
+ * predicates, both lie in the window and have equal keys (l == a included),
+ * one output (window start, l, a), l and a being row indices of `in`.  Rows
+ * are written in unspecified order; d_count[0] = the number of pairs, of
+ * which min(count, cap) are written (re-run with a larger cap to get all).
+ * d_count[1] = LMS_ERANGE if event times span 2^30 panes or more.
+ * Workspace: lms_window_self_join_workspace(in->nrows). */
+size_t lms_window_self_join_workspace(int64_t nrows);
+int lms_window_self_join(const lms_batch* in, const lms_pred* preds, int32_t npred, int32_t key_col,
+                         const lms_window* w, int64_t* out_wstart, uint32_t* out_l, uint32_t* out_a, int64_t cap,
+                         int64_t* d_count, void* workspace, size_t ws_bytes, lms_stream stream);
+
 /* ---- Many micro-batches per launch -------------------------------------------
  * The same windowed group-by over nbatch micro-batches of one schema, with
  * every stage run as one persistent launch over all batches (a fixed grid

@@ -123,6 +123,23 @@ class lms_admit_stats(ctypes.Structure):
                 ("mean_maxlat_ms", ctypes.c_double)]
 
 
+class lms_keypart(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_int32), ("reserved", ctypes.c_int32), ("lo", ctypes.c_int64), ("hi", ctypes.c_int64)]
+
+
+class lms_having(ctypes.Structure):
+    _fields_ = [("agg", ctypes.c_int32), ("op", ctypes.c_int32), ("ival", ctypes.c_int64), ("fval", ctypes.c_double)]
+
+
+class lms_order(ctypes.Structure):
+    _fields_ = [("agg", ctypes.c_int32), ("descending", ctypes.c_int32)]
+
+
+class lms_qgroups(ctypes.Structure):
+    _fields_ = [("keys", ctypes.POINTER(ctypes.c_void_p)), ("wstart", ctypes.c_void_p),
+                ("aggs", ctypes.POINTER(ctypes.c_void_p)), ("cap", ctypes.c_int64)]
+
+
 class lms_tuning(ctypes.Structure):
     _fields_ = [("chunk_rows", ctypes.c_int32), ("part_rows", ctypes.c_int32), ("piece_rows", ctypes.c_int32),
                 ("grid_per_cu", ctypes.c_int32), ("lds_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -144,6 +161,14 @@ _SIGS = {
     "lms_window_agg": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _i32, _P(lms_window),
                                       _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz, _vp]),
     "lms_window_agg_emit": (ctypes.c_int, [_P(lms_groups), _i32, _vp, _vp, _sz, _vp]),
+    "lms_window_query_workspace": (_sz, [_P(lms_batch), _P(lms_keypart), _i32, _P(lms_window), _P(lms_agg), _i32,
+                                         _i32, _i64]),
+    "lms_window_query": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _P(lms_proj), _i32, _P(lms_keypart), _i32,
+                                        _P(lms_window), _P(lms_agg), _i32, _P(lms_having), _P(lms_order),
+                                        _P(lms_qgroups), _vp, _vp, _sz, _vp]),
+    "lms_window_self_join_workspace": (_sz, [_i64]),
+    "lms_window_self_join": (ctypes.c_int, [_P(lms_batch), _P(lms_pred), _i32, _i32, _P(lms_window), _vp, _vp, _vp,
+                                            _i64, _vp, _vp, _sz, _vp]),
     "lms_window_agg_multi_workspace": (_sz, [_P(lms_batch), _i32, _i32, _P(lms_window), _P(lms_agg), _i32]),
     "lms_window_agg_multi_prepare": (ctypes.c_int, [_P(lms_batch), _i32, _P(lms_pred), _i32, _P(lms_proj), _i32, _i32,
                                                     _P(lms_window), _P(lms_agg), _i32, _P(lms_groups), _vp, _vp, _sz,
@@ -406,6 +431,84 @@ def lms_window_agg(cols, key_col, window: Window, aggs, preds=(), projs=(), grou
                              _stream_handle(stream))
     _check(rc)
     return groups, d_count
+
+
+class QueryGroups:
+    """Device output columns of lms_window_query: one int64 column per key part."""
+
+    def __init__(self, cap: int, nkey: int, aggs, device):
+        self.cap = cap
+        self.keys = [torch.empty(max(cap, 1), dtype=torch.int64, device=device) for _ in range(nkey)]
+        self.wstart = torch.empty(max(cap, 1), dtype=torch.int64, device=device)
+        self.aggs = [torch.empty(max(cap, 1), dtype=torch.float64 if f == AVG else torch.int64, device=device)
+                     for f, _ in aggs]
+        self._kp = (ctypes.c_void_p * max(1, nkey))(*[t.data_ptr() for t in self.keys])
+        self._ap = (ctypes.c_void_p * max(1, len(self.aggs)))(*[t.data_ptr() for t in self.aggs])
+        self.c = lms_qgroups(self._kp, self.wstart.data_ptr(), self._ap, cap)
+
+
+def lms_window_query(cols, keys, window: Window, aggs, preds=(), projs=(), having=None, order=None, cap=None,
+                     groups: QueryGroups | None = None, d_count=None, workspace=None, stream=None):
+    """Enqueues a windowed query with a composite key, HAVING and ORDER BY.
+
+    keys: [(col, lo, hi)] (lo/hi: the column's value domain; ignored for one
+    key); having: (agg index, op, value); order: (agg index, descending).
+    Returns (groups, d_count)."""
+    b = _Batch(cols)
+    n = b.batch.nrows
+    dev = cols[0].device
+    aggs = list(aggs)
+    keys = [tuple(k) if len(k) == 3 else (k[0], 0, 0) for k in keys]
+    if groups is None:
+        if cap is None:
+            slide = window.slide or window.length
+            cap = n * (-(-window.length // slide))
+        groups = QueryGroups(cap, len(keys), aggs, dev)
+    if d_count is None:
+        d_count = torch.zeros(2, dtype=torch.int64, device=dev)
+    pa, npred = _preds(preds)
+    pr, nproj = _projs(projs)
+    aa = (lms_agg * max(1, len(aggs)))(*[lms_agg(f, c) for f, c in aggs])
+    ka = (lms_keypart * max(1, len(keys)))(*[lms_keypart(int(c), 0, int(lo), int(hi)) for c, lo, hi in keys])
+    w = window.c()
+    hv = None
+    if having is not None:
+        k, op, v = having
+        hv = lms_having(int(k), int(op), 0 if isinstance(v, float) else int(v), float(v))
+    od = lms_order(int(order[0]), 1 if order[1] else 0) if order is not None else None
+    need = _lib.lms_window_query_workspace(ctypes.byref(b.batch), ka, len(keys), ctypes.byref(w), aa, len(aggs),
+                                           1 if order is not None else 0, groups.cap)
+    ws = _ws(workspace, need, dev, stream)
+    rc = _lib.lms_window_query(ctypes.byref(b.batch), pa, npred, pr, nproj, ka, len(keys), ctypes.byref(w), aa,
+                               len(aggs), ctypes.byref(hv) if hv is not None else None,
+                               ctypes.byref(od) if od is not None else None, ctypes.byref(groups.c),
+                               d_count.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    _check(rc)
+    return groups, d_count
+
+
+def lms_window_self_join(cols, key_col, window: Window, preds=(), cap=None, out=None, d_count=None, workspace=None,
+                         stream=None):
+    """Enqueues the windowed self-join; returns ((wstart, l, a), d_count)."""
+    b = _Batch(cols)
+    n = b.batch.nrows
+    dev = cols[0].device
+    if out is None:
+        cap = max(1, n) if cap is None else cap
+        out = (torch.empty(cap, dtype=torch.int64, device=dev), torch.empty(cap, dtype=torch.int32, device=dev),
+               torch.empty(cap, dtype=torch.int32, device=dev))
+    cap = out[0].numel() if cap is None else cap
+    if d_count is None:
+        d_count = torch.zeros(2, dtype=torch.int64, device=dev)
+    pa, npred = _preds(preds)
+    w = window.c()
+    need = _lib.lms_window_self_join_workspace(n)
+    ws = _ws(workspace, need, dev, stream)
+    rc = _lib.lms_window_self_join(ctypes.byref(b.batch), pa, npred, key_col, ctypes.byref(w), out[0].data_ptr(),
+                                   out[1].data_ptr(), out[2].data_ptr(), cap, d_count.data_ptr(), ws.data_ptr(),
+                                   ws.numel(), _stream_handle(stream))
+    _check(rc)
+    return out, d_count
 
 
 def lms_window_agg_emit(aggs, workspace, groups: Groups | None = None, cap: int | None = None, d_count=None,

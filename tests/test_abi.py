@@ -113,3 +113,32 @@ def test_workspace_queries_are_positive_and_grow():
     small = lms.lms_window_agg_workspace(cpu_cols(16), 1, lms.Window(0, 10, 2), [(lms.COUNT, 0), (lms.SUM, 2)])
     assert small > 0
     assert lms.pane_limit(4) >= 1024
+
+
+@pytest.mark.parametrize("keys,having,order,msg", [
+    ([], None, None, "nkey"),
+    ([(1, 0, 9)] * 5, None, None, "nkey"),
+    ([(1, 0, 1 << 40), (2, 0, 1 << 30)], None, None, "2^62"),
+    ([(1, 5, 4), (2, 0, 1)], None, None, "hi < lo"),
+    ([(3, 0, 9), (2, 0, 1)], None, None, "integer column"),
+    ([(1, 0, 9), (2, 0, 1)], (3, 0, 1), None, "HAVING"),
+    ([(1, 0, 9), (2, 0, 1)], None, (2, True), "ORDER BY"),
+])
+def test_window_query_rejects_bad_arguments(keys, having, order, msg):
+    with pytest.raises(lms.LmsError) as e:
+        lms.lms_window_query(cpu_cols(), keys, lms.Window(0, 10, 0), [(lms.COUNT, 0), (lms.SUM, 2)], having=having,
+                             order=order, cap=4, d_count=torch.zeros(2, dtype=torch.int64), workspace=_HostWs(),
+                             stream=0)
+    assert e.value.code == lms.LMS_EINVAL
+    assert msg in str(e.value)
+
+
+def test_window_self_join_rejects_bad_arguments():
+    with pytest.raises(lms.LmsError) as e:
+        lms.lms_window_self_join(cpu_cols(), 3, lms.Window(0, 10, 0), cap=4, d_count=torch.zeros(2, dtype=torch.int64),
+                                 workspace=_HostWs(), stream=0)
+    assert "key column" in str(e.value)
+    with pytest.raises(lms.LmsError):
+        lms.lms_window_self_join(cpu_cols(), 1, lms.Window(0, 10, 20), cap=4,
+                                 d_count=torch.zeros(2, dtype=torch.int64), workspace=_HostWs(), stream=0)
+    assert lms._lib.lms_window_self_join_workspace(1000) > 0

@@ -86,14 +86,20 @@ def run_serving(args, log):
     t = serve.Traffic((0.1e6, 1e6, 5e6, 10e6), args.serve_step_s)
     arr = t.arrivals_ms()
     data = serve.StreamData(arr, 1 << 24)
-    for mode in ("served", "baseline"):
-        eng = serve.Engine(data, mode=mode, model=model, log=log)
+    # served with learned micro-batch sizing (the cost model's processing
+    # term in Eq. 6), served with Eq. 4's AvgThPut, and the plain form
+    forms = [("served", "served", "learned"), ("served_eq6", "served", "analytic"), ("baseline", "baseline", None)]
+    if model is None:
+        forms = [f for f in forms if f[0] != "served_eq6"]
+    for name, mode, sizing in forms:
+        eng = serve.Engine(data, mode=mode, model=model, sizing=sizing or "analytic", log=log)
         res = eng.run()
-        out[mode] = {k: res[k] for k in ("p50_ms", "p99_ms", "Mrows_s", "wall_s", "hbm_waits")}
-        out[mode]["queries"] = {q: {k: v[k] for k in ("p50_ms", "p99_ms", "maxlat_p99_ms", "batches", "cpu_batches",
-                                                      "breakdown_pct")}
+        out[name] = {k: res[k] for k in ("sizing", "p50_ms", "p99_ms", "Mrows_s", "wall_s", "hbm_waits")}
+        keys = ("p50_ms", "p99_ms", "maxlat_p99_ms", "over_bound_pct", "proc_est_err_pct", "batches",
+                "mean_batch_rows", "cpu_batches", "breakdown_pct")
+        out[name]["queries"] = {q: {k: v[k] for k in keys}
                                 for q, v in res["queries"].items()}
-        log(f"serving {mode}: {json.dumps(res)}")
+        log(f"serving {name}: {json.dumps(res)}")
         del eng
     out["stream_rows"] = int(len(arr) * serve.DS_ROWS)
     return out

@@ -405,6 +405,9 @@ typedef struct {
   double avg_thput_rows_per_ms, mean_maxlat_ms;
 } lms_admit_stats;
 typedef struct lms_admit lms_admit;
+typedef struct lms_mlp_model lms_mlp_model;
+typedef struct lms_op_desc lms_op_desc;
+typedef struct lms_batch_stats lms_batch_stats;
 int lms_admit_create(const lms_admit_params* p, lms_admit** out);
 /* arrival_ms/rows: host arrays of the n_new datasets that arrived since the
  * last poll (any order).  On admission the buffer is handed over whole, in
@@ -412,6 +415,21 @@ int lms_admit_create(const lms_admit_params* p, lms_admit** out);
 int lms_admit_poll(lms_admit* a, double now_ms, int64_t n_new, const double* arrival_ms, const int64_t* rows,
                    lms_admit_decision* out);
 int lms_admit_done(lms_admit* a, int64_t rows, double proc_ms, double maxlat_ms);
+/* Learned micro-batch sizing (Algorithm 1 with a learned Eq. 6 processing
+ * term).  After this call the processing term of `rows` buffered rows is the
+ * predicted time of the query's operation chain ops[0..nops) on a micro-batch
+ * of that many rows -- each operation on the device lms_plan picks in
+ * LMS_PLAN_LEARNED mode, with per_batch's statistics and rows and
+ * batch_bytes = bytes_per_row * rows (distinct_keys capped at rows) -- times
+ * the ratio of measured to predicted processing time over the batches
+ * reported since (1 before the first).  model, ops and per_batch are copied.
+ * model == NULL returns to Eq. 4's AvgThPut.  Host-only. */
+int lms_admit_set_model(lms_admit* a, const lms_mlp_model* model, const lms_op_desc* ops, int32_t nops,
+                        const lms_batch_stats* per_batch, double bytes_per_row);
+/* The processing term (ms) the controller would use for `rows` buffered rows
+ * now (0 while it is unknown: analytic sizing before the first completed
+ * batch); -1 for bad arguments. */
+double lms_admit_predict_ms(const lms_admit* a, int64_t rows);
 int lms_admit_get_stats(const lms_admit* a, lms_admit_stats* out);
 void lms_admit_free(lms_admit* a);
 
@@ -502,7 +520,7 @@ typedef enum {
 typedef enum { LMS_DEV_CPU = 0, LMS_DEV_GPU = 1 } lms_device;
 typedef enum { LMS_PLAN_ANALYTIC = 0, LMS_PLAN_LEARNED = 1 } lms_plan_mode;
 
-typedef struct {
+typedef struct lms_op_desc {
   int32_t kind;     /* lms_opkind */
   int32_t ncols;    /* columns the operation reads (learned mode) */
   double base_cost; /* <= 0: Table II default */
@@ -510,7 +528,7 @@ typedef struct {
   double slide_s;   /* window slide in seconds, 0 = tumbling (learned mode) */
 } lms_op_desc;
 
-typedef struct {
+typedef struct lms_batch_stats {
   int64_t batch_bytes; /* size of the micro-batch in bytes */
   int32_t num_cores;   /* NumCores (Table I): number of data partitions */
   int32_t reserved;
@@ -554,7 +572,7 @@ int lms_plan(const lms_op_desc* ops, int32_t nops, const lms_batch_stats* st, co
 #define LMS_MLP_OUT 2
 #define LMS_MLP_NPARAMS (64 * 12 + 64 + 64 * 64 + 64 + 2 * 64 + 2)
 typedef struct lms_mlp lms_mlp;
-typedef struct {
+typedef struct lms_mlp_model {
   float params[LMS_MLP_NPARAMS];
 } lms_mlp_model;
 int lms_mlp_create(uint64_t seed, lms_mlp** out);

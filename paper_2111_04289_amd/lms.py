@@ -184,6 +184,8 @@ _SIGS = {
     "lms_admit_poll": (ctypes.c_int, [_vp, ctypes.c_double, _i64, _vp, _vp, _P(lms_admit_decision)]),
     "lms_admit_done": (ctypes.c_int, [_vp, _i64, ctypes.c_double, ctypes.c_double]),
     "lms_admit_get_stats": (ctypes.c_int, [_vp, _P(lms_admit_stats)]),
+    "lms_admit_set_model": (ctypes.c_int, [_vp, _vp, _vp, _i32, _vp, ctypes.c_double]),
+    "lms_admit_predict_ms": (ctypes.c_double, [_vp, _i64]),
     "lms_admit_free": (None, [_vp]),
     "lms_set_tuning": (ctypes.c_int, [_P(lms_tuning)]),
     "lms_get_tuning": (ctypes.c_int, [_P(lms_tuning)]),
@@ -699,6 +701,27 @@ class Admission:
 
     def done(self, rows, proc_ms, maxlat_ms):
         _check(_lib.lms_admit_done(self.handle, int(rows), float(proc_ms), float(maxlat_ms)))
+
+    def set_model(self, model, ops, selectivity=1.0, distinct_keys=0, num_cores=1, interval_s=0.0,
+                  bytes_per_row=24.0):
+        """Learned sizing: Eq. 6's processing term from the learned cost model.
+
+        ops: [(kind, ncols, window_s, slide_s)] of the query's operation chain;
+        model None returns to Eq. 4's AvgThPut."""
+        import numpy as np
+        if model is None:
+            _check(_lib.lms_admit_set_model(self.handle, None, None, 0, None, 0.0))
+            return
+        keep = np.ascontiguousarray(model, dtype=np.float32)
+        if keep.size != MLP_NPARAMS:
+            raise ValueError("model must hold MLP_NPARAMS float32 parameters")
+        arr = (lms_op_desc * len(ops))(*[lms_op_desc(int(k), int(c), 0.0, float(w), float(sl)) for k, c, w, sl in ops])
+        st = lms_batch_stats(0, int(num_cores), 0, 0, float(selectivity), int(distinct_keys), float(interval_s))
+        _check(_lib.lms_admit_set_model(self.handle, keep.ctypes.data, arr, len(ops), ctypes.byref(st),
+                                        float(bytes_per_row)))
+
+    def predict_ms(self, rows) -> float:
+        return float(_lib.lms_admit_predict_ms(self.handle, int(rows)))
 
     def stats(self) -> dict:
         st = lms_admit_stats()

@@ -52,6 +52,10 @@ SLIDE_AGGS = [(lms.COUNT, 0), (lms.SUM, 2), (lms.MIN, 2), (lms.MAX, 2), (lms.AVG
 TUMBLE_AGGS = [(lms.COUNT, 0)]
 IN_BYTES = {"fp": 20, "tumble": 16, "slide": 24, "join": 8}  # device input bytes per row
 MAX_EMIT_WINDOWS = 8
+# the operation chain of each query as the learned cost model sees it:
+# (kind, columns read, window s, slide s), selectivity
+SIZING_OPS = {"fp": ([(lms.OP_FILTER, 3, 0.0, 0.0)], 0.3), "tumble": ([(lms.OP_AGG, 4, 1.0, 0.0)], 1.0),
+              "slide": ([(lms.OP_AGG, 4, 10.0, 1.0)], 0.3), "join": ([(lms.OP_JOIN, 1, 0.0, 0.0)], 1.0)}
 
 
 # ---- traffic ------------------------------------------------------------------------
@@ -146,6 +150,7 @@ class Batch:
     need: int = 0
     device: int = lms.DEV_GPU
     stage: int = 0
+    pred_proc: float = 0.0  # the controller's Eq. 6 processing term at admission (0: none yet)
     ev: object = None
     keep: list = field(default_factory=list)
     future: object = None
@@ -166,6 +171,8 @@ class Query:
         self.inflight = []
         self.lat = []           # per-dataset end-to-end latency (ms)
         self.maxlat = []        # per-batch MaxLat (ms)
+        self.bound = []         # the latency bound each batch is held to (ms)
+        self.est_err = []       # |predicted - measured| / measured processing time per batch
         self.proc = []
         self.batch_rows = []
         # time spent per step, as in the paper's overhead breakdown (ms):
@@ -184,6 +191,11 @@ class Query:
                 self.ctl = lms.Admission(slide_ms=0.0, poll_ms=eng.poll_ms)
             else:
                 self.ctl = lms.Admission(deadline_ms=eng.bound_ms, poll_ms=eng.poll_ms)
+            if eng.sizing == "learned":
+                # learned micro-batch sizing: Eq. 6's processing term from the cost model
+                ops, sel = SIZING_OPS[name]
+                self.ctl.set_model(eng.model, ops, selectivity=sel, distinct_keys=1 << 20, num_cores=eng.cores,
+                                   bytes_per_row=IN_BYTES[name])
         self.state = None
         self.drained = False
         self.closed = False  # the end-of-stream batch has taken the controller's buffer
@@ -208,8 +220,9 @@ class Query:
 class Engine:
     def __init__(self, data: StreamData, mode="served", queries=QUERIES, poll_ms=10.0, bound_ms=1000.0,
                  trigger_ms=1000.0, slots=2, hbm_budget=None, model=None, cores=None, max_keys=1 << 20,
-                 collect=False, placement=True, log=None):
+                 collect=False, placement=True, sizing="learned", log=None):
         self.data, self.mode = data, mode
+        self.sizing = sizing if model is not None else "analytic"
         self.poll_ms, self.bound_ms, self.trigger_ms = poll_ms, bound_ms, trigger_ms
         self.slots = slots
         self.model = model
@@ -241,6 +254,15 @@ class Engine:
 
     def now(self):
         return (time.perf_counter() - self.t0) * 1e3
+
+    def batch_bound(self, q):
+        """The latency bound a batch of q is held to: SlideTime for the sliding
+        window, the window length for the tumbling one (its admission target, the
+        mean past MaxLat of Eq. 3, moves with the batches themselves), and the
+        deadline for the windowless queries."""
+        if q.name in ("slide", "tumble"):
+            return 1000.0
+        return self.bound_ms
 
     def ev_ms(self, ev):
         return self.t0_ev + self.ev0.elapsed_time(ev)
@@ -353,6 +375,9 @@ class Engine:
             lat = b.t_done - arr
             q.lat.append(lat)
             maxlat = float(lat.max())
+            q.bound.append(self.batch_bound(q))
+            if b.pred_proc > 0:
+                q.est_err.append(abs(b.pred_proc - (b.t_done - b.t_admit)) / max(b.t_done - b.t_admit, 1e-3))
             q.maxlat.append(maxlat)
             q.proc.append(b.t_done - b.t_admit)
             q.t_buffer += max(0.0, b.t_admit - b.oldest)
@@ -402,6 +427,7 @@ class Engine:
                         q.next_batch_ds = d1
                         b = Batch(q.name, d0, d1, (d1 - d0) * DS_ROWS, now, float(arr[d0]))
                         b.need = q.need(b.rows)
+                        b.pred_proc = q.ctl.predict_ms(b.rows)
                         t0 = time.perf_counter()
                         b.device = self.place(q, b.rows, (now - last_admit[q.name]) / 1e3)
                         q.t_map += (time.perf_counter() - t0) * 1e3
@@ -474,7 +500,8 @@ class Engine:
             tot = sum(parts.values()) or 1.0
             return {k: round(100.0 * v / tot, 3) for k, v in parts.items()}
 
-        out = {"mode": self.mode, "stream_ms": round(end_ms, 1), "queries": {}}
+        out = {"mode": self.mode, "sizing": self.sizing if self.mode == "served" else "fixed trigger",
+               "stream_ms": round(end_ms, 1), "queries": {}}
         total = 0
         wall = self.now()
         for q in self.queries.values():
@@ -488,6 +515,11 @@ class Engine:
                 "maxlat_p50_ms": round(float(np.percentile(ml, 50)), 2),
                 "maxlat_p99_ms": round(float(np.percentile(ml, 99)), 2),
                 "mean_proc_ms": round(float(np.mean(q.proc)), 3) if q.proc else 0.0,
+                # batches whose MaxLat (Eq. 5) exceeded the bound they were admitted under
+                "over_bound_pct": round(100.0 * float(np.mean(np.array(q.maxlat) > np.array(q.bound))), 2)
+                if q.maxlat else 0.0,
+                # median relative error of the admission's processing-time estimate
+                "proc_est_err_pct": round(100.0 * float(np.median(q.est_err)), 1) if q.est_err else None,
                 "breakdown_pct": breakdown(q)}
         out["rows_per_query"] = total // max(1, len(self.queries))
         out["Mrows_s"] = round(total / max(1, len(self.queries)) / (wall / 1e3) / 1e6, 3)
@@ -515,6 +547,9 @@ def main():
     ap.add_argument("--mode", nargs="+", default=["served", "baseline"])
     ap.add_argument("--model", default=None, help="MLP parameters (.npy) for learned placement")
     ap.add_argument("--no-placement", action="store_true")
+    ap.add_argument("--bound-ms", type=float, default=1000.0, help="latency bound of the windowless queries")
+    ap.add_argument("--sizing", default="learned", choices=("learned", "analytic"),
+                    help="Eq. 6 processing term: the learned cost model, or Eq. 4's AvgThPut")
     args = ap.parse_args()
 
     def log(m):
@@ -525,7 +560,8 @@ def main():
     for mode in args.mode:
         t = Traffic(tuple(args.rates), args.step_s)
         log(f"{mode}: rates {args.rates} rows/s, {args.step_s} s each")
-        res, _ = serve(t, mode, args.pool_rows, model=model, log=log, placement=not args.no_placement)
+        res, _ = serve(t, mode, args.pool_rows, model=model, log=log, placement=not args.no_placement,
+                       sizing=args.sizing, bound_ms=args.bound_ms)
         log(json.dumps(res))
         out[mode] = res
     print(json.dumps(out), flush=True)

@@ -121,3 +121,41 @@ def test_native_controller_stats():
     assert st["batches_done"] == 1 and st["avg_thput_rows_per_ms"] == pytest.approx(5.0)
     with pytest.raises(lms.LmsError):
         a.poll(0.0, [1.0], [-5])
+
+
+def _constant_model(log_cpu_ms, log_gpu_ms):
+    """An MLP whose weights are zero: its outputs are the last-layer biases."""
+    from paper_2111_04289_amd import lms
+    p = np.zeros(lms.MLP_NPARAMS, np.float32)
+    p[-2], p[-1] = log_cpu_ms, log_gpu_ms
+    return p
+
+
+def test_learned_sizing_closed_form():
+    """Learned Eq. 6 term: a constant model predicts exp(min output) ms per
+    operation (MapDevice takes the cheaper device); the completed batches'
+    measured/predicted ratio then scales it."""
+    from paper_2111_04289_amd import lms
+    a = lms.Admission(deadline_ms=100.0, poll_ms=10.0)
+    a.set_model(_constant_model(np.log(5.0), np.log(3.0)), [(lms.OP_FILTER, 3, 0, 0), (lms.OP_JOIN, 1, 0, 0)])
+    assert a.predict_ms(1000) == pytest.approx(6.0, rel=1e-6)
+    d = a.poll(0.0, [0.0], [1000])  # the first batch is admitted at once
+    assert d.admit == 1
+    a.done(1000, 12.0, 20.0)  # measured twice the prediction
+    assert a.predict_ms(4000) == pytest.approx(12.0, rel=1e-6)
+    # buffered at 100 ms: admitted once 100 ms >= buff + 12 + 10 (poll)
+    assert a.poll(170.0, [100.0], [1000]).admit == 0  # 70 + 12 + 10 = 92
+    d = a.poll(178.0)                                   # 78 + 12 + 10 = 100
+    assert d.admit == 1 and d.est_maxlat_ms == pytest.approx(90.0, rel=1e-9)
+    # back to Eq. 4: AvgThPut = 1000 rows / 12 ms
+    a.set_model(None, [])
+    assert a.predict_ms(3000) == pytest.approx(36.0, rel=1e-9)
+
+
+def test_learned_sizing_rejects_bad_arguments():
+    from paper_2111_04289_amd import lms
+    a = lms.Admission(deadline_ms=100.0)
+    with pytest.raises(ValueError):
+        a.set_model(np.zeros(7, np.float32), [(lms.OP_FILTER, 3, 0, 0)])
+    with pytest.raises(lms.LmsError):
+        a.set_model(_constant_model(0.0, 0.0), [])

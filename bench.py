@@ -38,7 +38,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rows", type=int, default=1 << 24)
-    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 23)
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 22)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-trace", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--streams", type=int, default=3, choices=(1, 3),
@@ -310,6 +310,20 @@ def main():
     ms_per_step = total_ms / args.steps
     value = n / (ms_per_step / 1e3) / 1e6
 
+    # measured device copy rate (what a kernel that reads and writes each byte
+    # once can reach here), beside the published peak
+    src = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 5 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
     traffic = traffic_record()
     groups_n = counts["groups"]
     # algorithmic bytes of the windowed group-by: referenced columns read once
@@ -336,20 +350,10 @@ def main():
     torch.cuda.empty_cache()
     serving = run_serving(args, log) if args.serve_step_s > 0 else None
 
-    cpu = None
+    cpu = cpu1 = None
     if not args.no_cpu_baseline:
-        import oracle
-        s = min(args.cpu_sample_rows, n)
-        sample = [c[:s] for c in cols_np]
-        log(f"cpu oracle on {s} rows")
-        t = time.perf_counter()
-        oracle.filter_project(sample, [(2, 0, cut)], [0, 1], [(2, 2, 0)])
-        oracle.window_agg(sample, 1, 0, 10000, 1000, 0, [(0, 0), (1, 2), (2, 2), (3, 2), (4, 3)], [(2, 0, cut)])
-        oracle.hash_join(bk_np, bp_np, sample[1])
-        dt = time.perf_counter() - t
-        cpu = {"value": round(s / dt / 1e6, 4), "unit": "Mrows/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {s} rows of the {n}-row batch through filter+project, windowed group-by and join",
-               "seconds": round(dt, 2), "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
+        cpu1 = cpu_oracle(cols_np, bk_np, bp_np, cut, min(args.cpu_sample_rows, n), 1, log)
+        cpu = cpu_oracle(cols_np, bk_np, bp_np, cut, n, min(16, os.cpu_count() or 1), log)
 
     out = {
         "metric": "Mrows/s windowed group-by (% HBM roofline); p50/p99 micro-batch latency",
@@ -377,8 +381,11 @@ def main():
                      "traffic": (round(traffic["fetch_bytes"] + traffic["write_bytes"]) if traffic else None),
                      "traffic_fetch_write": ([round(traffic["fetch_bytes"]), round(traffic["write_bytes"])]
                                              if traffic else None),
-                     "alg_bytes_per_launch": wa_bytes, "ms_per_launch": round(wa_ms, 4)},
+                     "alg_bytes_per_launch": wa_bytes, "ms_per_launch": round(wa_ms, 4),
+                     "measured_copy_GB_s": round(copy_gbs, 1),
+                     "frac_of_copy": round(achieved / copy_gbs, 4) if achieved else None},
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
         "ops": ops,
         "join_build_ms": round(build_ms, 3),
         "window_status": status,
@@ -387,6 +394,45 @@ def main():
         "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def cpu_oracle(cols_np, bk_np, bp_np, cut, s, threads, log):
+    """The oracle on the first s rows, on `threads` host threads: filter+project
+    and the join on row ranges, the windowed group-by on key-hash partitions
+    (every group's rows are in one partition, so the partitions' results are
+    disjoint).  The C oracle releases the interpreter lock while it runs;
+    splitting the rows is inside the timed region."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    sample = [c[:s] for c in cols_np]
+    aggs = [(0, 0), (1, 2), (2, 2), (3, 2), (4, 3)]
+    log(f"cpu oracle on {s} rows, {threads} threads")
+    t = time.perf_counter()
+    if threads == 1:
+        oracle.filter_project(sample, [(2, 0, cut)], [0, 1], [(2, 2, 0)])
+        oracle.window_agg(sample, 1, 0, 10000, 1000, 0, aggs, [(2, 0, cut)])
+        oracle.hash_join(bk_np, bp_np, sample[1])
+    else:
+        bounds = np.linspace(0, s, threads + 1).astype(np.int64)
+        part = (sample[1].view(np.uint64) * np.uint64(0x9E3779B97F4A7C15)) >> np.uint64(60)
+        with ThreadPoolExecutor(threads) as ex:
+            jobs = [ex.submit(oracle.filter_project, [c[bounds[i]:bounds[i + 1]] for c in sample], [(2, 0, cut)],
+                              [0, 1], [(2, 2, 0)]) for i in range(threads)]
+            jobs += [ex.submit(oracle.hash_join, bk_np, bp_np, sample[1][bounds[i]:bounds[i + 1]])
+                     for i in range(threads)]
+            for j in jobs:
+                j.result()
+            sel = [np.flatnonzero(part % np.uint64(threads) == i) for i in range(threads)]
+            jobs = [ex.submit(oracle.window_agg, [c[ix] for c in sample], 1, 0, 10000, 1000, 0, aggs, [(2, 0, cut)])
+                    for ix in sel]
+            for j in jobs:
+                j.result()
+    dt = time.perf_counter() - t
+    return {"value": round(s / dt / 1e6, 4), "unit": "Mrows/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {s} rows of the {len(cols_np[0])}-row batch through filter+project, windowed "
+                      f"group-by and join" + ("" if threads == 1 else
+                                              "; row ranges per thread, key-hash partitions for the group-by"),
+            "seconds": round(dt, 2), "host_cpu": _cpu_model(), "host_nproc": os.cpu_count()}
 
 
 def _cpu_model():

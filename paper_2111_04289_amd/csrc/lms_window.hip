@@ -475,17 +475,47 @@ __device__ __forceinline__ void staged_rows(const WinArgs& a, int v, const int64
   }
 }
 
-// Scatter the passing rows, as (key, pane, value columns), to their partition.
-// The predicate columns are read first; every other column a passing row
-// needs is then loaded for all kUnroll rows of a thread before the first LDS
-// cursor atomic, so the loads overlap, and rows that fail read one shared row
-// in their place, so a selective predicate leaves most lines unread.
+// One staged record at r: key (8 B) at 0, 8-byte values at their offsets,
+// then the pane, the 4-byte values and the padding -- consecutive words from
+// pane_off (an 8-byte boundary) to the record's end, written two per 8-byte
+// store (fewer partial-line writes than one store per field).
 template <int MA>
-__device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
+__device__ __forceinline__ void put_record(const WinArgs& a, char* r, int64_t key, uint64_t qp,
+                                           const uint64_t (&val)[MA]) {
+  *(int64_t*)r = key;
+  uint32_t wd[MA + 2];
+  wd[0] = (uint32_t)qp;
+#pragma unroll
+  for (int t = 1; t < MA + 2; ++t) wd[t] = 0;
+#pragma unroll
+  for (int v = 0; v < MA; ++v) {
+    if (v < a.nval) {
+      if (a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_F32) {
+        const int t = (a.voff[v] - a.pane_off) >> 2;
+#pragma unroll
+        for (int tt = 1; tt <= MA; ++tt)
+          if (tt == t) wd[tt] = (uint32_t)val[v];
+      } else {
+        *(uint64_t*)(r + a.voff[v]) = val[v];
+      }
+    }
+  }
+  const int nw = (a.rec - a.pane_off) >> 2;  // even
+#pragma unroll
+  for (int t = 0; t < MA + 2; t += 2)
+    if (t < nw) *(uint2*)(r + a.pane_off + 4 * t) = make_uint2(wd[t], wd[t + 1]);
+}
+
+// The passing rows of chunk w, handed to sink(partition, key, pane, values).
+// The predicate columns are read first; every other column a passing row
+// needs is then loaded for all kUnroll rows of a thread before the first
+// record is handed over, so the loads overlap, and rows that fail read one
+// shared row in their place, so a selective predicate leaves most lines
+// unread.
+template <int MA, int TPB, class Sink>
+__device__ void scatter_rows(const WinArgs& a, uint32_t w, Sink sink) {
   // eight value columns per row would hold too many loads in registers at 4 rows
   constexpr int kU = MA <= 6 ? kUnroll : 2;
-  for (int p = threadIdx.x; p < a.nparts; p += kScatterTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
-  __syncthreads();
   const int64_t b0 = a.hdr[0];
   const int64_t lo = (int64_t)w * a.chunk;
   const int64_t hi = min(a.q.nrows, lo + a.chunk);
@@ -494,13 +524,13 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
   const void* tc = a.q.col[a.ts_col];
   const int tdt = a.q.dt[a.ts_col];
   bool range_err = false;
-  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)kScatterTPB * kU) {
+  for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)TPB * kU) {
     bool ok[kU];
     int64_t key[kU], ts[kU], idx[kU];
     uint64_t val[kU][MA];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      idx[u] = b + (int64_t)u * kScatterTPB;
+      idx[u] = b + (int64_t)u * TPB;
       ok[u] = idx[u] < hi;
     }
     rows_pass<kU>(a.q, idx, ok, lo);
@@ -521,7 +551,6 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if (!ok[u]) continue;
-      const uint32_t pos = atomicAdd(&cursor[part_of(fmix64((uint64_t)key[u]), a.pbits)], 1u);
       const int64_t rel = ts[u] - a.origin - b0 * a.pane;
       uint64_t qp = 0;
       if (rel < 0) range_err = true;
@@ -530,36 +559,83 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
         range_err = true;
         qp = 0;
       }
-      char* const r = a.srec + (size_t)pos * a.rec;
-      *(int64_t*)r = key[u];
-      // the pane, the 4-byte values and the padding are consecutive words from
-      // pane_off to the end of the record, both 8-byte boundaries: written two
-      // per 8-byte store (fewer partial-line writes than one store per field)
-      uint32_t wd[MA + 2];
-      wd[0] = (uint32_t)qp;
-#pragma unroll
-      for (int t = 1; t < MA + 2; ++t) wd[t] = 0;
-#pragma unroll
-      for (int v = 0; v < MA; ++v) {
-        if (v < a.nval) {
-          if (a.vdt[v] == LMS_I32 || a.vdt[v] == LMS_F32) {
-            const int t = (a.voff[v] - a.pane_off) >> 2;
-#pragma unroll
-            for (int tt = 1; tt <= MA; ++tt)
-              if (tt == t) wd[tt] = (uint32_t)val[u][v];
-          } else {
-            *(uint64_t*)(r + a.voff[v]) = val[u][v];
-          }
-        }
-      }
-      const int nw = (a.rec - a.pane_off) >> 2;  // even
-#pragma unroll
-      for (int t = 0; t < MA + 2; t += 2)
-        if (t < nw) *(uint2*)(r + a.pane_off + 4 * t) = make_uint2(wd[t], wd[t + 1]);
+      sink(part_of(fmix64((uint64_t)key[u]), a.pbits), key[u], qp, val[u]);
     }
   }
   if (range_err) win_status(a, LMS_ERANGE);
   __syncthreads();
+}
+
+// Scatter the passing rows of chunk w, as (key, pane, value columns), each to
+// the next slot of its partition's segment for this chunk.
+template <int MA>
+__device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
+  for (int p = threadIdx.x; p < a.nparts; p += kScatterTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
+  __syncthreads();
+  scatter_rows<MA, kScatterTPB>(a, w, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
+    const uint32_t pos = atomicAdd(&cursor[part], 1u);
+    put_record<MA>(a, a.srec + (size_t)pos * a.rec, key, qp, val);
+  });
+}
+
+// Staged scatter of one chunk (single-batch launch, one 1024-thread workgroup
+// per chunk): when the chunk's passing rows fit the LDS stage, they are first
+// written there sorted by partition (the chunk's own histogram gives each
+// partition's first slot), then copied out 8-byte word by word, consecutive
+// lanes writing consecutive words of a partition's segment.  Written straight
+// to the segments, a wave's records went to 64 different cache lines per
+// store; copied out, a store covers a few.  A chunk with more passing rows
+// than the stage holds takes the direct path.
+constexpr int kStTPB = 1024;
+constexpr size_t kStLds = 160 * 1024 - 512;  // dynamic LDS of the staged scatter
+
+__host__ __device__ inline uint32_t stage_cap(int nparts, int rec) {
+  return (uint32_t)((kStLds - 16 - 8 * (size_t)nparts) / (size_t)(rec + 2));
+}
+
+template <int MA>
+__global__ __launch_bounds__(kStTPB) void k_wa_scatter_st(WinArgs a) {
+  extern __shared__ __align__(16) char st_lds[];
+  __shared__ uint32_t scratch[kStTPB / 64 + 1];
+  const uint32_t w = xcd_chunk(blockIdx.x, (uint32_t)a.g1);
+  if (w >= (uint32_t)a.g1) return;
+  const int np = a.nparts;
+  const uint32_t cap = stage_cap(np, a.rec);
+  uint32_t* const cur = (uint32_t*)st_lds;          // np: next slot of each partition
+  uint32_t* const gof = cur + np;                    // np: staging index of slot 0's partition segment
+  uint16_t* const spart = (uint16_t*)(gof + np);     // cap: partition of each staged record
+  char* const stage = (char*)align_up((size_t)(spart + cap), 16);
+  for (int p = threadIdx.x; p < np; p += kStTPB) cur[p] = a.H[(size_t)p * a.g1 + w];
+  __syncthreads();
+  const uint32_t total = block_scan_array<kStTPB>(cur, np, scratch);  // cur = first slot of each partition
+  if (total > cap) {  // does not fit the stage: straight to the segments
+    for (int p = threadIdx.x; p < np; p += kStTPB) cur[p] = a.Off[(size_t)p * a.g1 + w];
+    __syncthreads();
+    scatter_rows<MA, kStTPB>(a, w, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
+      const uint32_t pos = atomicAdd(&cur[part], 1u);
+      put_record<MA>(a, a.srec + (size_t)pos * a.rec, key, qp, val);
+    });
+    return;
+  }
+  for (int p = threadIdx.x; p < np; p += kStTPB) gof[p] = a.Off[(size_t)p * a.g1 + w] - cur[p];
+  __syncthreads();
+  scatter_rows<MA, kStTPB>(a, w, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
+    const uint32_t slot = atomicAdd(&cur[part], 1u);
+    spart[slot] = (uint16_t)part;
+    put_record<MA>(a, stage + (size_t)slot * a.rec, key, qp, val);
+  });
+  // (scatter_rows ends with a barrier)
+  const uint32_t nw = (uint32_t)a.rec >> 3;
+  const uint32_t words = total * nw;
+  const float inv = 1.0f / (float)nw;
+  for (uint32_t i = threadIdx.x; i < words; i += kStTPB) {
+    uint32_t r = (uint32_t)((float)i * inv);  // record of word i: a float estimate, corrected exactly
+    while (r * nw > i) --r;
+    while ((r + 1) * nw <= i) ++r;
+    const uint32_t k = i - r * nw;
+    const uint32_t dst = gof[spart[r]] + r;
+    ((uint64_t*)(a.srec + (size_t)dst * a.rec))[k] = ((const uint64_t*)(stage + (size_t)r * a.rec))[k];
+  }
 }
 
 template <int MA>
@@ -2003,7 +2079,15 @@ void launch_tail(const Plan& p, const WinArgs& a, size_t plds, hipStream_t st) {
   // workgroups as the CUs hold at once: one per CU (a 1024-thread workgroup
   // already fills each SIMD's register budget at 4 waves)
   const int resident = num_cus();
-  LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScatterTPB), plds, st, a);
+  if constexpr (MA <= 6) {
+    static const int st_rc = check_hip(hipFuncSetAttribute((const void*)k_wa_scatter_st<MA>,
+                                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kStLds),
+                                       "LDS attribute");
+    if (st_rc) return;
+    LMS_LAUNCH("k_wa_scatter", k_wa_scatter_st<MA>, dim3(xcd_slots(p.g1)), dim3(kStTPB), kStLds, st, a);
+  } else {
+    LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScatterTPB), plds, st, a);
+  }
   LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(std::min(p.max_items, resident)), dim3(kAggTPB), p.lds, st, a);
   LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(std::min(p.nparts, resident)), dim3(kAggTPB), p.lds, st, a);
 }

@@ -167,16 +167,20 @@ __device__ __forceinline__ void win_status(const WinArgs& a, int code) {
   atomicMin((long long*)&a.hdr[5], (long long)code);
 }
 
+// Every thread of the block copies its share of the words (a single thread
+// copying the whole struct went through private memory, one word at a time);
+// thread 0 then marks the slot valid after the block's barrier.
 __device__ __forceinline__ void save_args(const WinArgs& a) {
-  *a.saved = a;
-  a.hdr[6] = kSavedMagic;
+  const uint32_t* src = (const uint32_t*)&a;
+  uint32_t* dst = (uint32_t*)a.saved;
+  for (uint32_t i = threadIdx.x; i < sizeof(WinArgs) / 4; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) a.hdr[6] = kSavedMagic;
 }
 
 __global__ void k_wa_init(WinArgs a) {
-  if (threadIdx.x == 0) {
-    init_batch(a);
-    save_args(a);
-  }
+  if (threadIdx.x == 0) init_batch(a);
+  save_args(a);
 }
 
 // Chunk processed by workgroup slot g of a launch over n chunks (slots padded
@@ -331,44 +335,36 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
   // workgroups finish close together.  The estimate (microseconds; measured
   // on the 16M-row sliding query: an unsplit item about 30 + 5 per 1000 rows,
   // a piece about 7 + 3.4) picks one of 64 classes; the order within a class
-  // is arbitrary, as is the claim order itself.
+  // is arbitrary, as is the claim order itself.  The full pieces of a split
+  // partition share a class, so they take consecutive slots with one claim.
+  // (Plain code over LDS arrays: item records built in lambdas went through
+  // private memory.)
   __shared__ uint32_t ccls[64];
   auto cls = [](uint32_t est) { return 63u - min(63u, est); };
-  // f(first item, number of items, their class): the full pieces of a split
-  // partition share a class, so they take consecutive slots with one claim
-  auto each_item = [&](int p, auto f) {
-    const uint32_t v = r[p], k = kc[p], ib = base[p], s0 = st[p];
-    if (k == 0) return;
-    Item it;
-    it.p = p;
-    it.first = ib;
-    it.reserved[0] = it.reserved[1] = it.reserved[2] = 0;
-    if (v > rs) {
-      it.kp = k;
-      it.lo = s0;
-      it.hi = s0 + rs;
-      if (k > 1) f(it, k - 1, cls(7u + rs / 300u));
-      it.lo = s0 + (k - 1) * rs;
-      it.hi = s0 + v;
-      f(it, 1u, cls(7u + (it.hi - it.lo) / 300u));
-    } else {
-      uint32_t hi = s0 + v;
-      if (v <= pack) {  // extend over the rest of the bucket
-        const uint32_t b = s0 / pack;
-        int q = p + 1;
-        while (q < np && (r[q] == 0 || (r[q] <= pack && st[q] / pack == b))) ++q;
-        hi = q < np ? st[q] : total;
-      }
-      it.kp = 1;
-      it.lo = s0;
-      it.hi = hi;
-      f(it, 1u, cls(30u + (hi - s0) / 200u));
+  uint32_t* const ihi = base;  // the item start array is not needed any more: end of an unsplit item
+  for (int p = threadIdx.x; p < np; p += kPlanTPB) {
+    const uint32_t v = r[p], s0 = st[p];
+    uint32_t hi = s0 + v;
+    if (v > 0 && v <= pack && kc[p] != 0) {  // a packed item extends over the rest of its bucket
+      const uint32_t b = s0 / pack;
+      int q = p + 1;
+      while (q < np && (r[q] == 0 || (r[q] <= pack && st[q] / pack == b))) ++q;
+      hi = q < np ? st[q] : total;
     }
-  };
+    ihi[p] = hi;
+  }
   if (threadIdx.x < 64) ccls[threadIdx.x] = 0;
   __syncthreads();
-  for (int p = threadIdx.x; p < np; p += kPlanTPB)
-    each_item(p, [&](const Item&, uint32_t n, uint32_t c) { atomicAdd(&ccls[c], n); });
+  for (int p = threadIdx.x; p < np; p += kPlanTPB) {
+    const uint32_t v = r[p], k = kc[p];
+    if (k == 0) continue;
+    if (v > rs) {
+      if (k > 1) atomicAdd(&ccls[cls(7u + rs / 300u)], k - 1);
+      atomicAdd(&ccls[cls(7u + (v - (k - 1) * rs) / 300u)], 1u);
+    } else {
+      atomicAdd(&ccls[cls(30u + (ihi[p] - st[p]) / 200u)], 1u);
+    }
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
@@ -379,17 +375,25 @@ __device__ void plan_items(const WinArgs& a, uint32_t* r, uint32_t* st, uint32_t
     }
   }
   __syncthreads();
+  auto put = [&](uint32_t at, uint32_t p, uint32_t lo, uint32_t hi, uint32_t kp) {
+    uint4* const d = (uint4*)&a.items[at];
+    d[0] = make_uint4(p, lo, hi, 0u);
+    d[1] = make_uint4(kp, 0u, 0u, 0u);
+  };
   for (int p = threadIdx.x; p < np; p += kPlanTPB) {
-    each_item(p, [&](Item it, uint32_t n, uint32_t c) {
-      const uint32_t at = atomicAdd(&ccls[c], n);
-      for (uint32_t j = 0; j < n; ++j) {  // n > 1 only for full pieces, rs rows apart
-        a.items[at + j] = it;
-        it.lo += rs;
-        it.hi += rs;
+    const uint32_t v = r[p], k = kc[p], s0 = st[p];
+    if (k > 0) {
+      if (v > rs) {
+        if (k > 1) {
+          const uint32_t at = atomicAdd(&ccls[cls(7u + rs / 300u)], k - 1);
+          for (uint32_t j = 0; j + 1 < k; ++j) put(at + j, (uint32_t)p, s0 + j * rs, s0 + (j + 1) * rs, k);
+        }
+        put(atomicAdd(&ccls[cls(7u + (v - (k - 1) * rs) / 300u)], 1u), (uint32_t)p, s0 + (k - 1) * rs, s0 + v, k);
+      } else {
+        put(atomicAdd(&ccls[cls(30u + (ihi[p] - s0) / 200u)], 1u), (uint32_t)p, s0, ihi[p], 1u);
       }
-    });
-    const uint32_t k = kc[p], ib = base[p], s0 = st[p];
-    a.pinfo[p].first = ib;
+    }
+    a.pinfo[p].first = 0;
     a.pinfo[p].kp = k;
     a.pinfo[p].start = s0;
     a.pinfo[p].reserved = 0;
@@ -413,7 +417,7 @@ __global__ __launch_bounds__(kPlanTPB) void k_wa_scanp(WinArgs a) {
   __shared__ uint32_t r[kMaxParts], st[kMaxParts], kc[kMaxParts], base[kMaxParts];
   __shared__ uint32_t scratch[kPlanTPB / 64 + 1];
   plan_items(a, r, st, kc, base, scratch);
-  if (threadIdx.x == 0) save_args(a);
+  save_args(a);
 }
 
 // Per-(partition, chunk) write offsets: partition start plus an exclusive scan

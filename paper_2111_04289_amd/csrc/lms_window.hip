@@ -856,6 +856,43 @@ __device__ __forceinline__ uint32_t group_hash(uint64_t gid) {
   return h;
 }
 
+// Slot of `want` in an open-addressing table of n (a power of two) 64-bit
+// slots, linear probing from `start`; claims the first empty slot if `want`
+// is absent.  Four consecutive slots are read per step, all issued before
+// the first is tested: the probe is bound by LDS round trips, and a wave runs
+// as long as its longest probe, so fewer dependent steps per slot count more
+// than the few extra reads.  Slots only ever go from empty to taken while
+// rows are inserted, so slots seen taken by another value stay so, and a
+// value is always in the first empty-or-matching slot of its sequence (a lost
+// claim is re-examined: the winner may have written the same value).
+// Returns -1 if the table is full.
+__device__ __forceinline__ int probe_claim(uint64_t* tab, uint32_t n, uint32_t start, uint64_t want, uint64_t empty) {
+  const uint32_t mask = n - 1;
+  uint32_t pos = start;
+  for (uint32_t seen = 0; seen < n;) {
+    uint64_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = __atomic_load_n(&tab[(pos + u) & mask], __ATOMIC_RELAXED);
+    int hit = -1;
+#pragma unroll
+    for (int u = 3; u >= 0; --u)
+      if (c[u] == want || c[u] == empty) hit = u;
+    if (hit < 0) {
+      pos += 4;
+      seen += 4;
+      continue;
+    }
+    const uint32_t slot = (pos + (uint32_t)hit) & mask;
+    if (c[hit] == want) return (int)slot;
+    const uint64_t old = atomicCAS((unsigned long long*)&tab[slot], (unsigned long long)empty,
+                                   (unsigned long long)want);
+    if (old == empty || old == want) return (int)slot;
+    pos += (uint32_t)hit + 1;  // taken by another value meanwhile: go on after it
+    seen += (uint32_t)hit + 1;
+  }
+  return -1;
+}
+
 // Inserts one element; returns false if a table is full.
 template <int MA>
 __device__ __forceinline__ bool insert(const WinArgs& a, Lds& s, const Elem<MA>& x, uint64_t h) {
@@ -864,45 +901,11 @@ __device__ __forceinline__ bool insert(const WinArgs& a, Lds& s, const Elem<MA>&
     kid = a.ek;
     s.keys[a.ek] = kEmptyKey;
   } else {
-    kid = -1;
-    uint32_t slot = (uint32_t)h & (uint32_t)(a.ek - 1);
-    for (int t = 0; t < a.ek; ++t) {
-      const uint64_t cur = __atomic_load_n(&s.keys[slot], __ATOMIC_RELAXED);
-      if (cur == (uint64_t)x.key) {
-        kid = (int)slot;
-        break;
-      }
-      if (cur == kEmptyKey) {
-        const uint64_t old = atomicCAS((unsigned long long*)&s.keys[slot], (unsigned long long)kEmptyKey,
-                                       (unsigned long long)x.key);
-        if (old == kEmptyKey || old == (uint64_t)x.key) {
-          kid = (int)slot;
-          break;
-        }
-      }
-      slot = (slot + 1) & (uint32_t)(a.ek - 1);
-    }
+    kid = probe_claim(s.keys, (uint32_t)a.ek, (uint32_t)h & (uint32_t)(a.ek - 1), (uint64_t)x.key, kEmptyKey);
     if (kid < 0) return false;
   }
   const uint64_t gid = ((uint64_t)kid << 32) | x.pane;
-  int g = -1;
-  uint32_t slot = group_hash(gid) & (uint32_t)(a.eg - 1);
-  for (int t = 0; t < a.eg; ++t) {
-    const uint64_t cur = __atomic_load_n(&s.gid[slot], __ATOMIC_RELAXED);
-    if (cur == gid) {
-      g = (int)slot;
-      break;
-    }
-    if (cur == kEmptyGid) {
-      const uint64_t old = atomicCAS((unsigned long long*)&s.gid[slot], (unsigned long long)kEmptyGid,
-                                     (unsigned long long)gid);
-      if (old == kEmptyGid || old == gid) {
-        g = (int)slot;
-        break;
-      }
-    }
-    slot = (slot + 1) & (uint32_t)(a.eg - 1);
-  }
+  const int g = probe_claim(s.gid, (uint32_t)a.eg, group_hash(gid) & (uint32_t)(a.eg - 1), gid, kEmptyGid);
   if (g < 0) return false;
   atomicAdd(&s.gcnt[g], x.cnt);
 #pragma unroll

@@ -547,6 +547,24 @@ typedef struct {
 } lms_cost_params;
 
 double lms_table2_base_cost(int32_t kind);
+
+/* Online inflection-point regression (Sec. III-E, Eq. 10), the tuner of the
+ * analytic cost model: after each micro-batch, lms_infpt_record stores the
+ * InfPT it ran with, its throughput (rows per ms of processing) and its
+ * MaxLat (Eq. 5).  lms_infpt_next fits InfPT = b0 + b1 * Throughput +
+ * b2 * Latency by least squares over the last `history` records (0: all),
+ * evaluates it at the target throughput (the largest seen) and the target
+ * latency (target_latency, or the mean past MaxLat if <= 0), and returns the
+ * result times 1 + jitter * u, u uniform in [-1, 1] from SplitMix64 seeded
+ * with `seed` (one draw per call; the exploration that keeps the fit
+ * identifiable).  With fewer than three records, collinear regressors or a
+ * prediction that is not positive, the previous InfPT (init_bytes at first)
+ * is kept.  Host-only; returns -1 for a NULL handle. */
+typedef struct lms_infpt lms_infpt;
+int lms_infpt_create(double init_bytes, int32_t history, double jitter, uint64_t seed, lms_infpt** out);
+int lms_infpt_record(lms_infpt* t, double infpt_used, double thput, double maxlat);
+double lms_infpt_next(lms_infpt* t, double target_latency);
+void lms_infpt_free(lms_infpt* t);
 int lms_plan(const lms_op_desc* ops, int32_t nops, const lms_batch_stats* st, const lms_cost_params* cp,
              int32_t* out_dev, double* out_cost);
 

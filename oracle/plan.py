@@ -54,3 +54,51 @@ def map_device(bases, batch_bytes, num_cores, infpt=INFPT0, base_trans=BASE_TRAN
             plan[o] = CPU
         costs[o] = cpu if plan[o] == CPU else gpu
     return plan, costs
+
+
+def splitmix64(state):
+    """One step of SplitMix64 (Steele, Lea and Flood): returns (output, new state)."""
+    m = (1 << 64) - 1
+    state = (state + 0x9E3779B97F4A7C15) & m
+    z = state
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m
+    return z ^ (z >> 31), state
+
+
+class InfPTRegression:
+    """Eq. 10 (Sec. III-E): InfPT = b0 + b1 * Throughput + b2 * Latency, fitted
+    by least squares on the recorded micro-batches (the last `history`, all if
+    0) and evaluated at the target throughput (the largest seen) and the
+    target latency (given, else the mean past MaxLat).  Reading (no value is
+    printed for these): fewer than three records, collinear regressors or a
+    non-positive prediction keep the previous InfPT; the returned value is
+    multiplied by 1 + jitter * u with u uniform in [-1, 1] from SplitMix64 so
+    the recorded InfPTs vary and the fit is identifiable."""
+
+    def __init__(self, init_bytes=INFPT0, history=0, jitter=0.1, seed=0):
+        self.cur = float(init_bytes)
+        self.history = history
+        self.jitter = jitter
+        self.state = seed
+        self.rec = []
+
+    def record(self, infpt_used, thput, maxlat):
+        self.rec.append((float(thput), float(maxlat), float(infpt_used)))
+
+    def next(self, target_latency=0.0):
+        import numpy as np
+        rec = self.rec[-self.history:] if self.history else self.rec
+        if len(rec) >= 3:
+            x = np.array([[1.0, t, lat] for t, lat, _ in rec])
+            y = np.array([v for _, _, v in rec])
+            if np.linalg.matrix_rank(x, tol=1e-9 * np.abs(x).max()) == 3:
+                beta = np.linalg.lstsq(x, y, rcond=None)[0]
+                tmax = max(t for t, _, _ in self.rec)
+                lat = target_latency if target_latency > 0 else float(np.mean([lat for _, lat, _ in self.rec]))
+                pred = beta[0] + beta[1] * tmax + beta[2] * lat
+                if np.isfinite(pred) and pred > 0:
+                    self.cur = float(pred)
+        out, self.state = splitmix64(self.state)
+        u = (out >> 11) * 2.0 ** -53 * 2.0 - 1.0
+        return self.cur * (1.0 + self.jitter * u)

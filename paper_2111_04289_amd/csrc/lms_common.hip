@@ -223,3 +223,102 @@ extern "C" int lms_plan(const lms_op_desc* ops, int32_t nops, const lms_batch_st
   }
   return LMS_OK;
 }
+
+// ---- online inflection-point regression (Eq. 10) ----------------------------
+// After each micro-batch the controller records the InfPT it used with the
+// batch's throughput (rows per ms) and MaxLat; before the next one it fits
+// InfPT = b0 + b1 * Throughput + b2 * Latency by least squares over the last
+// `history` records (all if 0) and evaluates it at the targets: the largest
+// throughput seen and the target latency.  The regressors are centred and
+// scaled before the normal equations are solved, so the 3x3 system stays
+// well conditioned; with fewer than three records, collinear regressors or a
+// prediction that is not a positive finite number, the last InfPT is kept.
+// The value handed out is then multiplied by 1 + jitter * u, u uniform in
+// [-1, 1] from SplitMix64 (Steele, Lea and Flood's generator; one draw per
+// call): without it every record would carry the same InfPT and the fit
+// could never move it.
+struct lms_infpt {
+  double cur;
+  int32_t history;
+  double jitter;
+  uint64_t rng;
+  std::vector<double> x1, x2, y;
+};
+
+namespace {
+uint64_t splitmix64_next(uint64_t* s) {
+  uint64_t z = (*s += 0x9e3779b97f4a7c15ull);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+}  // namespace
+
+extern "C" int lms_infpt_create(double init_bytes, int32_t history, double jitter, uint64_t seed, lms_infpt** out) {
+  if (!out) return set_error(LMS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!(init_bytes > 0) || history < 0 || !(jitter >= 0 && jitter < 1))
+    return set_error(LMS_EINVAL, "bad inflection-point tuner parameters");
+  *out = new lms_infpt{init_bytes, history, jitter, seed, {}, {}, {}};
+  return LMS_OK;
+}
+
+extern "C" void lms_infpt_free(lms_infpt* t) { delete t; }
+
+extern "C" int lms_infpt_record(lms_infpt* t, double infpt_used, double thput, double maxlat) {
+  if (!t || !(infpt_used > 0) || !(thput >= 0) || !(maxlat >= 0)) return set_error(LMS_EINVAL, "bad record");
+  t->x1.push_back(thput);
+  t->x2.push_back(maxlat);
+  t->y.push_back(infpt_used);
+  return LMS_OK;
+}
+
+extern "C" double lms_infpt_next(lms_infpt* t, double target_latency) {
+  if (!t) return -1.0;
+  const size_t n = t->y.size();
+  const size_t lo = (t->history > 0 && n > (size_t)t->history) ? n - (size_t)t->history : 0;
+  const size_t m = n - lo;
+  if (m >= 3) {
+    double m1 = 0, m2 = 0, my = 0, tmax = t->x1[0], lsum = 0;
+    for (size_t i = 0; i < n; ++i) {
+      tmax = std::max(tmax, t->x1[i]);
+      lsum += t->x2[i];
+    }
+    for (size_t i = lo; i < n; ++i) {
+      m1 += t->x1[i];
+      m2 += t->x2[i];
+      my += t->y[i];
+    }
+    m1 /= (double)m;
+    m2 /= (double)m;
+    my /= (double)m;
+    double s1 = 0, s2 = 0;
+    for (size_t i = lo; i < n; ++i) {
+      s1 += (t->x1[i] - m1) * (t->x1[i] - m1);
+      s2 += (t->x2[i] - m2) * (t->x2[i] - m2);
+    }
+    s1 = std::sqrt(s1 / (double)m);
+    s2 = std::sqrt(s2 / (double)m);
+    if (s1 > 0 && s2 > 0) {
+      // centred, scaled regressors: the intercept is then the mean of y
+      double a11 = 0, a12 = 0, a22 = 0, r1 = 0, r2 = 0;
+      for (size_t i = lo; i < n; ++i) {
+        const double u = (t->x1[i] - m1) / s1, v = (t->x2[i] - m2) / s2, w = t->y[i] - my;
+        a11 += u * u;
+        a12 += u * v;
+        a22 += v * v;
+        r1 += u * w;
+        r2 += v * w;
+      }
+      const double det = a11 * a22 - a12 * a12;
+      if (det > 1e-9 * a11 * a22) {
+        const double c1 = (r1 * a22 - r2 * a12) / det, c2 = (a11 * r2 - a12 * r1) / det;
+        const double lat = target_latency > 0 ? target_latency : lsum / (double)n;
+        const double pred = my + c1 * (tmax - m1) / s1 + c2 * (lat - m2) / s2;
+        if (std::isfinite(pred) && pred > 0) t->cur = pred;
+      }
+    }
+  }
+  const double u = (double)(splitmix64_next(&t->rng) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+  return t->cur * (1.0 + t->jitter * u);
+}

@@ -216,6 +216,10 @@ _SIGS = {
     "lms_trace_enable": (ctypes.c_int, [_i32]),
     "lms_trace_read": (ctypes.c_int, [_P(lms_trace_stat), _i32]),
     "lms_table2_base_cost": (ctypes.c_double, [_i32]),
+    "lms_infpt_create": (ctypes.c_int, [ctypes.c_double, _i32, ctypes.c_double, ctypes.c_uint64, _P(_vp)]),
+    "lms_infpt_record": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+    "lms_infpt_next": (ctypes.c_double, [_vp, ctypes.c_double]),
+    "lms_infpt_free": (None, [_vp]),
     "lms_plan": (ctypes.c_int, [_P(lms_op_desc), _i32, _P(lms_batch_stats), _P(lms_cost_params), _P(ctypes.c_int32),
                                 _P(ctypes.c_double)]),
 }
@@ -906,6 +910,29 @@ def lms_plan(kinds, batch_bytes, num_cores, infpt_bytes=150.0 * 1024, base_trans
     cost = (ctypes.c_double * max(1, n))()
     _check(_lib.lms_plan(ops, n, ctypes.byref(st), ctypes.byref(cp), dev, cost))
     return list(dev)[:n], list(cost)[:n]
+
+
+class InfPTTuner:
+    """Eq. 10: online regression of the inflection point (lms_infpt_*)."""
+
+    def __init__(self, init_bytes=150.0 * 1024, history=0, jitter=0.1, seed=0):
+        h = ctypes.c_void_p()
+        _check(_lib.lms_infpt_create(float(init_bytes), int(history), float(jitter), int(seed), ctypes.byref(h)))
+        self.handle = h
+
+    def record(self, infpt_used, thput, maxlat):
+        _check(_lib.lms_infpt_record(self.handle, float(infpt_used), float(thput), float(maxlat)))
+
+    def next(self, target_latency=0.0) -> float:
+        return float(_lib.lms_infpt_next(self.handle, float(target_latency)))
+
+    def __del__(self):
+        try:
+            if self.handle:
+                _lib.lms_infpt_free(self.handle)
+                self.handle = None
+        except Exception:
+            pass
 
 
 # ---- learned placement model -------------------------------------------------------------

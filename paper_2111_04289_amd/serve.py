@@ -151,6 +151,7 @@ class Batch:
     device: int = lms.DEV_GPU
     stage: int = 0
     pred_proc: float = 0.0  # the controller's Eq. 6 processing term at admission (0: none yet)
+    infpt: float = 0.0      # InfPT the analytic MapDevice ran with (Eq. 10 tuning)
     ev: object = None
     keep: list = field(default_factory=list)
     future: object = None
@@ -196,6 +197,8 @@ class Query:
                 ops, sel = SIZING_OPS[name]
                 self.ctl.set_model(eng.model, ops, selectivity=sel, distinct_keys=1 << 20, num_cores=eng.cores,
                                    bytes_per_row=IN_BYTES[name])
+        # analytic MapDevice without a trained model: InfPT tuned online (Eq. 10)
+        self.infpt = lms.InfPTTuner(seed=QUERIES.index(name)) if eng.model is None else None
         self.state = None
         self.drained = False
         self.closed = False  # the end-of-stream batch has taken the controller's buffer
@@ -268,7 +271,7 @@ class Engine:
         return self.t0_ev + self.ev0.elapsed_time(ev)
 
     # ---- placement (MapDevice) ----------------------------------------------------------
-    def place(self, q: Query, rows: int, interval_s: float):
+    def place(self, q: Query, rows: int, interval_s: float, b=None):
         if not self.placement or q.name not in ("fp", "join"):
             return lms.DEV_GPU
         kind = lms.OP_FILTER if q.name == "fp" else lms.OP_JOIN
@@ -280,7 +283,10 @@ class Engine:
                                    selectivity=sel, distinct_keys=distinct, ncols=[ncols], window_s=[0],
                                    slide_s=[0], interval_s=interval_s)
         else:
-            devs, _ = lms.lms_plan([kind], rows * (4 * ncols + 4), self.cores)
+            infpt = q.infpt.next(self.batch_bound(q))
+            if b is not None:
+                b.infpt = infpt
+            devs, _ = lms.lms_plan([kind], rows * (4 * ncols + 4), self.cores, infpt_bytes=infpt)
         return devs[0]
 
     # ---- batch execution ------------------------------------------------------------------
@@ -385,6 +391,8 @@ class Engine:
             q.rows_done += b.rows
             if self.mode == "served":
                 q.ctl.done(b.rows, max(b.t_done - b.t_admit, 1e-3), maxlat)
+                if q.infpt is not None and b.infpt > 0:  # Eq. 10's record of this batch
+                    q.infpt.record(b.infpt, b.rows / max(b.t_done - b.t_admit, 1e-3), maxlat)
         if q.results is not None:
             q.results.append((b.d0, b.d1, [t.numpy() if hasattr(t, "numpy") else t for t in b.result]))
 
@@ -429,7 +437,7 @@ class Engine:
                         b.need = q.need(b.rows)
                         b.pred_proc = q.ctl.predict_ms(b.rows)
                         t0 = time.perf_counter()
-                        b.device = self.place(q, b.rows, (now - last_admit[q.name]) / 1e3)
+                        b.device = self.place(q, b.rows, (now - last_admit[q.name]) / 1e3, b)
                         q.t_map += (time.perf_counter() - t0) * 1e3
                         last_admit[q.name] = now
                         q.waiting.append(b)

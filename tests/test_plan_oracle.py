@@ -3,6 +3,8 @@ printed Table II and against closed-form decision thresholds."""
 import math
 import os
 
+import numpy as np
+
 import pytest
 
 from oracle import plan
@@ -84,3 +86,60 @@ def test_tie_stays_on_gpu():
     devs, _ = plan.map_device([0.2], x * plan.INFPT0, 1)
     cpu, gpu = 0.2 * x, 0.2 / x + 0.1 * x
     assert devs == [plan.GPU if not gpu > cpu else plan.CPU]
+
+
+# ---- Eq. 10: online inflection-point regression -------------------------------------------
+
+def test_splitmix64_reference_output():
+    # the generator's published first output for seed 0
+    out, state = plan.splitmix64(0)
+    assert out == 0xE220A8397B1DCDAF
+    assert state == 0x9E3779B97F4A7C15
+
+
+def test_infpt_regression_recovers_an_exact_linear_history():
+    r = plan.InfPTRegression(init_bytes=1000.0, jitter=0.0)
+    for thput, lat in [(10.0, 200.0), (20.0, 150.0), (15.0, 400.0), (40.0, 100.0), (30.0, 250.0)]:
+        r.record(1000.0 + 2.0 * thput + 3.0 * lat, thput, lat)
+    # target throughput = the largest seen (40), target latency given
+    assert r.next(target_latency=300.0) == pytest.approx(1000.0 + 2.0 * 40.0 + 3.0 * 300.0, rel=1e-12)
+    # target latency = the mean past MaxLat when none is given
+    assert r.next() == pytest.approx(1000.0 + 80.0 + 3.0 * 220.0, rel=1e-12)
+
+
+def test_infpt_regression_degenerate_histories_keep_the_value():
+    r = plan.InfPTRegression(init_bytes=5000.0, jitter=0.0)
+    r.record(5000.0, 10.0, 100.0)
+    r.record(5000.0, 20.0, 300.0)
+    assert r.next(100.0) == 5000.0  # two records: no fit
+    r.record(5000.0, 30.0, 500.0)  # latency = 20 * throughput - 100: collinear
+    assert r.next(100.0) == 5000.0
+    r.record(5000.0, 11.0, 999.0)
+    assert r.next(100.0) == pytest.approx(5000.0, rel=1e-12)  # constant InfPT: b1 = b2 = 0
+    q = plan.InfPTRegression(init_bytes=5000.0, jitter=0.0)
+    for thput, lat in [(10.0, 100.0), (20.0, 110.0), (30.0, 105.0)]:
+        q.record(1000.0 + 100.0 * thput - 10.0 * lat, thput, lat)  # InfPT falls with latency
+    assert q.next(1e6) == 5000.0  # a negative prediction at a huge latency target keeps the previous value
+    assert q.next(100.0) == pytest.approx(1000.0 + 3000.0 - 1000.0, rel=1e-9)
+
+
+def test_infpt_jitter_range_and_sequence():
+    r = plan.InfPTRegression(init_bytes=1000.0, jitter=0.1, seed=7)
+    vals = [r.next() for _ in range(200)]
+    assert min(vals) >= 900.0 and max(vals) <= 1100.0
+    assert max(vals) - min(vals) > 150.0  # the draws spread over the range
+
+
+@pytest.mark.parametrize("seed,history", [(0, 0), (1, 5), (2, 0), (3, 8)])
+def test_native_infpt_tuner_matches_oracle(seed, history):
+    lms = pytest.importorskip("paper_2111_04289_amd.lms")
+    rng = np.random.default_rng(seed)
+    o = plan.InfPTRegression(init_bytes=153600.0, history=history, jitter=0.1, seed=seed)
+    n = lms.InfPTTuner(init_bytes=153600.0, history=history, jitter=0.1, seed=seed)
+    for step in range(30):
+        target = float(rng.choice([0.0, 1000.0, 3000.0]))
+        a, b = o.next(target), n.next(target)
+        assert b == pytest.approx(a, rel=1e-9), step
+        thput, lat = float(rng.uniform(100, 5000)), float(rng.uniform(50, 1500))
+        o.record(a, thput, lat)
+        n.record(b, thput, lat)

@@ -70,3 +70,24 @@ class ConstructMicroBatch:
 
     def complete(self, rows, proc, max_lat):
         self.done.append((rows, proc, max_lat))
+
+
+def fixed_trigger_batches(trigger_ms, arrivals, proc_of, t_end):
+    """The default micro-batch model the paper starts from (Sec. II-B, Fig. 4(a)):
+    a batch is cut every trigger interval and holds every dataset that arrived
+    since the last cut; when processing overruns the interval, the next cut
+    waits for it to finish (the interval stretches).  One executor.
+    Returns [(cut time, datasets, MaxLat)] with MaxLat as in Eq. 5."""
+    out, nxt, t = [], 0, float(trigger_ms)
+    while t <= t_end:
+        batch = []
+        while nxt < len(arrivals) and arrivals[nxt] <= t:
+            batch.append(arrivals[nxt])
+            nxt += 1
+        if batch:
+            proc = proc_of(len(batch))
+            out.append((t, len(batch), (t - min(batch)) + proc))
+            t = max(t + trigger_ms, t + proc)
+        else:
+            t += trigger_ms
+    return out

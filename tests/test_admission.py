@@ -159,3 +159,58 @@ def test_learned_sizing_rejects_bad_arguments():
         a.set_model(np.zeros(7, np.float32), [(lms.OP_FILTER, 3, 0, 0)])
     with pytest.raises(lms.LmsError):
         a.set_model(_constant_model(0.0, 0.0), [])
+
+
+def simulate_one_executor(ctl, arrivals, proc_of, t_end, poll=10.0):
+    """Algorithm 1 on one executor: the controller is polled every `poll` ms
+    while no batch runs (the module is called whenever there is no valid
+    micro-batch); datasets arriving meanwhile reach it at the next idle poll."""
+    out, nxt, t, busy_until, pending = [], 0, 0.0, 0.0, []
+    while t <= t_end:
+        while nxt < len(arrivals) and arrivals[nxt] <= t:
+            pending.append((arrivals[nxt], 1000))
+            nxt += 1
+        if t >= busy_until:
+            ok, batch = ctl.poll_once(t, pending)
+            pending = []
+            if ok:
+                proc = proc_of(len(batch))
+                maxlat = (t - min(c for c, _ in batch)) + proc
+                ctl.complete(1000 * len(batch), proc, maxlat)
+                out.append((t, len(batch), maxlat))
+                busy_until = t + proc
+        t = round(t + poll, 6)
+    return out
+
+
+def test_fixed_trigger_latency_grows_and_slide_bound_holds():
+    """Fig. 4: one dataset per second, SlideTime 3 s, a 5 s trigger whose first
+    batch takes 6 s (one second over the trigger).  Processing grows with the
+    square of the datasets in a batch (a windowed self-join, as LR1, pairs
+    rows of the batch), so proc(n) = 0.24 n^2 s and proc(5) = 6 s.
+    Fixed trigger, by hand: cut at 5 s with datasets 1..5 (MaxLat 4 + 6 = 10 s);
+    the next cut waits for the first batch, at 11 s, with 6..11 (proc 8.64 s,
+    MaxLat 5 + 8.64); then 19.64 s with 12..19 (proc 15.36, MaxLat 23 s); then
+    35 s with 20..35 (MaxLat 15 + 61.44 s): batch size and MaxLat grow without
+    bound.  Algorithm 1 on the same traffic keeps MaxLat near the slide."""
+    from oracle.admission import fixed_trigger_batches
+
+    def proc(n):
+        return 240.0 * n * n
+
+    arr = [1000.0 * k for k in range(1, 200)]
+    fixed = fixed_trigger_batches(5000.0, arr, proc, 120_000.0)
+    assert fixed[:4] == [(5000.0, 5, 10000.0), (11000.0, 6, 13640.0), (19640.0, 8, 23000.0),
+                         (35000.0, 16, 76440.0)]
+    assert all(b[2] > a[2] and b[1] > a[1] for a, b in zip(fixed, fixed[1:]))
+    assert fixed[-1][2] > 100 * 3000
+
+    lm = simulate_one_executor(ConstructMicroBatch(slide_ms=3000), arr, proc, 120_000.0)
+    assert len(lm) > 50
+    assert sum(n for _, n, _ in lm) >= 115  # keeps up with the one-per-second traffic
+    lats = [m for _, _, m in lm]
+    # the estimate is linear in rows (Eq. 4) while the cost is not, so a batch
+    # of three overshoots now and then; most stay under the slide and none grows
+    assert max(lats) < 1.5 * 3000
+    assert sum(m < 3000 for m in lats) >= 0.9 * len(lats)
+    assert max(lats[len(lats) // 2:]) <= max(lats[:len(lats) // 2])

@@ -7,15 +7,15 @@
 // lie in the run of used slots that starts at its home slot, so a probe walks
 // from the home slot to the first unused slot.
 // Probe: one pass walks the chains (a row's walk stops at its match when the
-// build found no repeated key) and records each row's match count and first
-// payload (8 bytes per row, coalesced) with per-tile totals (a tile is
-// one wave's contiguous range); a scan of the tile counts; then a write pass
-// that ranks rows with a wave scan and a running offset, so the pairs come out
-// grouped by ascending probe row without global atomics or workgroup
-// barriers, and touches the table again only for rows with several matches.
-// Each thread walks the chains of several consecutive rows in lockstep to
-// overlap the random slot reads (the table is MALL-resident, not
-// L2-resident).
+// build found no repeated key; each lane walks its rows one after another,
+// independently of the other lanes) and records per row what the write pass
+// needs (a payload and a hit bit when no key repeats, else the match count
+// and first payload), with per-tile totals (a tile is one wave's contiguous
+// range); a scan of the tile counts; then a write pass that ranks the pairs
+// of each 64-row group (by the hit mask, or a wave scan of the counts) with a
+// running offset, so the pairs come out grouped by ascending probe row
+// without global atomics or workgroup barriers, and touches the table again
+// only for rows with several matches.
 #include <algorithm>
 
 #include "lms_internal.h"
@@ -41,7 +41,7 @@ namespace {
 
 constexpr int kTPB = 256;
 constexpr int kScanThreads = 1024;
-constexpr int kProbe = 2;  // probe rows per thread per round (measured: 4 rows at half the occupancy ran 20 % slower)
+constexpr int kProbe = 2;  // rows per lane per round of the write pass when keys repeat
 
 __global__ void k_jb_clear(JSlot* slots, uint64_t nslots, int64_t* d_mult) {
   const uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
@@ -98,7 +98,9 @@ struct ProbeArgs {
   int64_t n;
   int64_t chunk;
   int32_t ntiles;
-  uint64_t* hits;  // per probe row: match count << 32 | first payload
+  uint64_t* hits;     // per probe row: match count << 32 | first payload (keys may repeat)
+  uint32_t* pay;      // per probe row: its payload (no key repeats; aliases hits)
+  uint64_t* hitmask;  // per 64 probe rows: which of them matched (no key repeats)
   int64_t* tile_cnt;
   int64_t* tile_off;
   uint32_t* out_idx;
@@ -108,56 +110,9 @@ struct ProbeArgs {
   const int64_t* d_mult;  // largest number of build rows sharing one key
 };
 
-// Walks the probe chains of kProbe consecutive rows in lockstep, so their slot
-// loads are independent; calls hit(u, payload) for every match of row u, in
-// chain order.  With first_only (no key occurs twice in the table) a row's
-// walk ends at its match instead of at the end of the run.
-template <class F>
-__device__ __forceinline__ void walk_rows(const ProbeArgs& a, const int64_t (&k)[kProbe], const bool (&valid)[kProbe],
-                                          bool first_only, F hit) {
-  uint64_t s[kProbe];
-  bool active[kProbe];
-#pragma unroll
-  for (int u = 0; u < kProbe; ++u) {
-    s[u] = fmix64((uint64_t)k[u]) & a.mask;
-    active[u] = valid[u];
-  }
-  for (uint64_t t = 0; t <= a.mask; ++t) {
-    bool any = false;
-    // every row's slot is loaded, finished rows' again (their cursor stays in
-    // the table, and the line is still cached): loads under a per-row branch
-    // would each wait for the previous one
-    uint4 sl[kProbe];  // one 16-byte load per slot: (key lo, key hi, payload, used)
-#pragma unroll
-    for (int u = 0; u < kProbe; ++u) sl[u] = *(const uint4*)(a.slots + s[u]);
-    // all loads are issued before any is used (the compiler would otherwise
-    // sink a load into the branches that read its fields, one wait each)
-#pragma unroll
-    for (int u = 0; u < kProbe; ++u) asm volatile("" ::"v"(sl[u].x), "v"(sl[u].y), "v"(sl[u].z), "v"(sl[u].w));
-#pragma unroll
-    for (int u = 0; u < kProbe; ++u) {
-      if (!active[u]) continue;
-      if (!sl[u].w) {
-        active[u] = false;
-        continue;
-      }
-      if ((int64_t)(((uint64_t)sl[u].y << 32) | sl[u].x) == k[u]) {
-        hit(u, (int32_t)sl[u].z);
-        if (first_only) {
-          active[u] = false;
-          continue;
-        }
-      }
-      s[u] = (s[u] + 1) & a.mask;
-      any = true;
-    }
-    if (!any) break;
-  }
-}
-
 // Tiles belong to waves: wave tile t covers rows [t * chunk, (t + 1) * chunk),
-// processed in rounds of kProbe sub-rounds of 64 consecutive rows with lane l
-// on row b0 + u * 64 + l, so key loads and record stores are contiguous per
+// a multiple of 64 rows, processed in groups of 64 consecutive rows with lane
+// l on row b0 + u * 64 + l, so key loads and record stores are contiguous per
 // wave, and no step needs a workgroup barrier.
 constexpr int kWaveRows = 64 * kProbe * 16;
 
@@ -169,60 +124,98 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
-// The probe keys and the per-row records are touched once per pass, so they
-// are loaded and stored non-temporally: they then displace less of the hot
-// part of the table from L2 (measured: 3 % faster probe pass).  All kProbe
-// loads are issued unconditionally (rows past the tile read its first row)
-// inside one dtype branch, so none waits for another.
-__device__ __forceinline__ void stream_keys(const ProbeArgs& a, const int64_t (&idx)[kProbe],
-                                            const bool (&valid)[kProbe], int64_t safe, int64_t (&k)[kProbe]) {
-  if (a.kdt == LMS_I32) {
-    int32_t x[kProbe];
-#pragma unroll
-    for (int u = 0; u < kProbe; ++u) x[u] = __builtin_nontemporal_load((const int32_t*)a.pkey + (valid[u] ? idx[u] : safe));
-#pragma unroll
-    for (int u = 0; u < kProbe; ++u) k[u] = valid[u] ? (int64_t)x[u] : 0;
-  } else {
-    int64_t x[kProbe];
-#pragma unroll
-    for (int u = 0; u < kProbe; ++u) x[u] = __builtin_nontemporal_load((const int64_t*)a.pkey + (valid[u] ? idx[u] : safe));
-#pragma unroll
-    for (int u = 0; u < kProbe; ++u) k[u] = valid[u] ? x[u] : 0;
-  }
-}
+// Probe pass: walks every row's chain once and records, per row, what the
+// write pass needs, plus the wave tile's total.  When no key occurs twice in
+// the table (the build's largest multiplicity is at most one) the record is
+// the row's payload (4 bytes) and one bit of a per-64-row hit mask; otherwise
+// it is the match count and first payload (count << 32 | payload).
+//
+// The walks are lane-independent.  A wave takes its tile in batches of
+// kBatch rows; lane l owns rows l, l + 64, ... of a batch, whose keys it
+// loads (coalesced across the wave) into its own LDS entries, and walks them
+// one after another: when a row's walk ends the lane moves on to its next
+// row at once, so every slot load of the wave serves a walk still in
+// progress.  (A lockstep walk costs a wave as many slot loads as its longest
+// chain, about seven at load 0.5 over 128 rows against a mean of 1.34; the
+// probe's time follows the count of these scattered wave loads.)  A finished
+// row's record replaces its key in LDS and the batch's records are stored
+// coalesced.  Each lane touches only its own LDS entries, so no barrier is
+// needed.  Keys and records are touched once, so they are loaded and stored
+// non-temporally: they displace less of the table's hot lines from L2.
+constexpr int kBatch = 512;
+constexpr int kLaneRows = kBatch / 64;
 
-// Probe pass: walks every row's chain once and records, per row, its match
-// count and first payload (packed count << 32 | payload) for the write pass,
-// plus the wave tile's total.
+template <class K>
 __global__ __launch_bounds__(kTPB) void k_jp_probe(ProbeArgs a) {
+  __shared__ uint64_t stage[kTPB / 64][kBatch];
   const int64_t t = wave_tile();
   if (t >= a.ntiles) return;
   const int64_t lo = t * a.chunk;
   const int64_t hi = min(a.n, lo + a.chunk);
   const int lane = threadIdx.x & 63;
+  uint64_t* const st = stage[threadIdx.x >> 6] + lane;  // the lane's row j at st[j * 64]
   const bool first_only = *a.d_mult <= 1;
+  const K* const pk = (const K*)a.pkey;
   uint32_t c = 0;
-  for (int64_t b0 = lo; b0 < hi; b0 += 64 * kProbe) {
-    int64_t k[kProbe], idx[kProbe];
-    bool valid[kProbe];
-    uint32_t cnt[kProbe];
-    uint32_t first[kProbe];
+  for (int64_t b0 = lo; b0 < hi; b0 += kBatch) {
+    const int64_t nb = min<int64_t>(kBatch, hi - b0);
+    const int nv = lane < nb ? (int)((nb - lane + 63) >> 6) : 0;  // the lane's rows in the batch
+    K kr[kLaneRows];  // rows past the tile read the tile's first row
 #pragma unroll
-    for (int u = 0; u < kProbe; ++u) {
-      idx[u] = b0 + (int64_t)u * 64 + lane;
-      valid[u] = idx[u] < hi;
-      cnt[u] = 0;
-      first[u] = 0;
+    for (int j = 0; j < kLaneRows; ++j) {
+      const int64_t r = b0 + (int64_t)j * 64 + lane;
+      kr[j] = __builtin_nontemporal_load(pk + (r < hi ? r : lo));
     }
-    stream_keys(a, idx, valid, lo, k);
-    walk_rows(a, k, valid, first_only, [&](int u, int32_t pay) {
-      if (cnt[u] == 0) first[u] = (uint32_t)pay;
-      ++cnt[u];
-    });
 #pragma unroll
-    for (int u = 0; u < kProbe; ++u) {
-      if (valid[u]) __builtin_nontemporal_store(((uint64_t)cnt[u] << 32) | first[u], a.hits + idx[u]);
-      c += cnt[u];
+    for (int j = 0; j < kLaneRows; ++j) st[j * 64] = (uint64_t)(int64_t)kr[j];
+    int j = 0;
+    int64_t k = (int64_t)kr[0];
+    uint64_t s = fmix64((uint64_t)k) & a.mask;
+    uint32_t cnt = 0, first = 0;
+    for (;;) {
+      const bool act = j < nv;
+      if (!__ballot(act)) break;
+      // a lane without rows left reads slot 0 (one shared line)
+      const uint4 sl = *(const uint4*)(a.slots + (act ? s : 0));  // (key lo, key hi, payload, used)
+      // one 16-byte load: the compiler would otherwise split it into loads
+      // sunk into the branches that read the fields, one wait each
+      asm volatile("" ::"v"(sl.x), "v"(sl.y), "v"(sl.z), "v"(sl.w));
+      if (act) {
+        bool done = !sl.w;
+        if (!done && (int64_t)(((uint64_t)sl.y << 32) | sl.x) == k) {
+          if (cnt == 0) first = sl.z;
+          ++cnt;
+          done = first_only;
+        }
+        if (done) {
+          st[j * 64] = ((uint64_t)cnt << 32) | first;
+          c += cnt;
+          if (++j < nv) {
+            k = (int64_t)st[j * 64];
+            s = fmix64((uint64_t)k) & a.mask;
+            cnt = 0;
+            first = 0;
+          }
+        } else {
+          s = (s + 1) & a.mask;
+        }
+      }
+    }
+    if (first_only) {
+#pragma unroll
+      for (int j2 = 0; j2 < kLaneRows; ++j2) {
+        const int64_t g = b0 + (int64_t)j2 * 64;  // 64-aligned: tiles and batches are multiples of 64 rows
+        const uint64_t v = st[j2 * 64];
+        const uint64_t m = __ballot(g + lane < hi && (v >> 32) != 0);
+        if (g + lane < hi) __builtin_nontemporal_store((uint32_t)v, a.pay + g + lane);
+        if (lane == 0 && g < hi) __builtin_nontemporal_store(m, a.hitmask + (g >> 6));
+      }
+    } else {
+#pragma unroll
+      for (int j2 = 0; j2 < kLaneRows; ++j2) {
+        const int64_t r = b0 + (int64_t)j2 * 64 + lane;
+        if (r < hi) __builtin_nontemporal_store(st[j2 * 64], a.hits + r);
+      }
     }
   }
   c = wave_sum(c);
@@ -251,6 +244,34 @@ __global__ __launch_bounds__(kTPB) void k_jp_write(ProbeArgs a) {
   const int64_t hi = min(a.n, lo + a.chunk);
   const int lane = threadIdx.x & 63;
   int64_t run = a.tile_off[t];
+  if (*a.d_mult <= 1) {
+    // one match at most per row: a 64-row group's pairs are ranked by its hit
+    // mask; kGroups groups' masks and payloads are loaded together
+    constexpr int kGroups = 4;
+    const uint64_t below = (1ull << lane) - 1;
+    for (int64_t b0 = lo; b0 < hi; b0 += 64 * kGroups) {
+      uint64_t m[kGroups];
+      uint32_t p[kGroups];
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) {
+        const int64_t r = b0 + (int64_t)g * 64;
+        m[g] = r < hi ? a.hitmask[r >> 6] : 0;
+        p[g] = r + lane < hi ? __builtin_nontemporal_load(a.pay + r + lane) : 0;
+      }
+#pragma unroll
+      for (int g = 0; g < kGroups; ++g) {
+        if ((m[g] >> lane) & 1) {
+          const int64_t o = run + __popcll(m[g] & below);
+          if (o < a.cap) {
+            a.out_idx[o] = (uint32_t)(b0 + (int64_t)g * 64 + lane);
+            a.out_pay[o] = (int32_t)p[g];
+          }
+        }
+        run += __popcll(m[g]);
+      }
+    }
+    return;
+  }
   for (int64_t b0 = lo; b0 < hi; b0 += 64 * kProbe) {
     int64_t idx[kProbe];
     uint64_t h[kProbe];
@@ -323,10 +344,13 @@ size_t jp_workspace(int64_t n, ProbeArgs* a, void* base) {
   int64_t* cnt = c.take<int64_t>(std::max(1, p.ntiles));
   int64_t* off = c.take<int64_t>(std::max(1, p.ntiles));
   uint64_t* hits = c.take<uint64_t>(std::max<int64_t>(1, n));
+  uint64_t* mask = c.take<uint64_t>(std::max<int64_t>(1, (n + 63) / 64));
   if (a) {
     a->tile_cnt = cnt;
     a->tile_off = off;
     a->hits = hits;
+    a->pay = (uint32_t*)hits;
+    a->hitmask = mask;
   }
   return c.size();
 }
@@ -451,7 +475,10 @@ extern "C" int lms_hash_join(const lms_join_table* t, const lms_batch* probe, in
     LMS_LAUNCH("k_jp_empty", k_jp_empty, dim3(1), dim3(64), 0, st, d_count);
   } else {
     const unsigned wgs = (unsigned)((p.ntiles + kTPB / 64 - 1) / (kTPB / 64));  // one wave per tile
-    LMS_LAUNCH("k_jp_probe", k_jp_probe, dim3(wgs), dim3(kTPB), 0, st, a);
+    if (kdt == LMS_I32)
+      LMS_LAUNCH("k_jp_probe", k_jp_probe<int32_t>, dim3(wgs), dim3(kTPB), 0, st, a);
+    else
+      LMS_LAUNCH("k_jp_probe", k_jp_probe<int64_t>, dim3(wgs), dim3(kTPB), 0, st, a);
     LMS_LAUNCH("k_jp_scan", k_jp_scan, dim3(1), dim3(kScanThreads), 0, st, a);
     LMS_LAUNCH("k_jp_write", k_jp_write, dim3(wgs), dim3(kTPB), 0, st, a);
   }

@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-stream comparison")
     ap.add_argument("--batches", type=int, default=256)
     ap.add_argument("--tuning", default=None, help="tuning JSON written by the autotuner (default: the packaged one)")
+    ap.add_argument("--placement-ops", type=int, default=300,
+                    help="held-out operations for the learned-vs-analytic placement comparison (0 skips it)")
     ap.add_argument("--serve-step-s", type=float, default=3.0,
                     help="seconds per rate step of the serving comparison (0 skips it)")
     return ap.parse_args()
@@ -208,6 +210,32 @@ def run_batched(args, torch, lms, datagen, cols, dev):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     lms.set_tuning()
+    return res
+
+
+def run_placement(args, log):
+    """The packaged learned placement model against the analytic cost model on
+    operations it was not trained on: each operation (filter-project, tumbling
+    or sliding aggregation, join; rows log-uniform up to 2^21) is timed on both
+    devices, transfers included, and each policy is charged the measured time
+    of the device it picks."""
+    from paper_2111_04289_amd import placement
+    params = placement.load_model()
+    if params is None:
+        return None
+    cores = min(16, os.cpu_count() or 1)
+    pool = placement.Pool(1 << 22)
+    rng = np.random.default_rng(0)
+    for op in placement.OPS:  # warm up both devices
+        cfg = {"op": op, "rows": 4096, "sel": 0.3, "window_s": 10, "slide_s": 1}
+        cols = pool.batch(rng, 4096)
+        placement.run_gpu(pool, cfg, cols)
+        placement.run_cpu(pool, cfg, cols, cores)
+    held = placement.collect(pool, args.placement_ops, 12345, cores, 1 << 21, 1 << 21)
+    res = placement.evaluate(held, params, cores)
+    res["cores"] = cores
+    log(f"placement {res}")
+    del pool
     return res
 
 
@@ -406,6 +434,7 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     serving = run_serving(args, log) if args.serve_step_s > 0 else None
+    placement_res = run_placement(args, log) if args.placement_ops > 0 else None
 
     cpu = cpu1 = None
     if not args.no_cpu_baseline:
@@ -450,6 +479,7 @@ def main():
         "small_batch": small,
         "batched": batched,
         "serving": serving,
+        "placement": placement_res,
     }
     print(json.dumps(out), flush=True)
 

@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--calib", action="store_true",
                     help="also run a 256 MiB device-to-device copy (scale reference for HBM byte counters)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched uneven-stream comparison")
+    ap.add_argument("--no-small", action="store_true", help="skip the 65,536-row micro-batch latency")
     ap.add_argument("--batches", type=int, default=256)
     ap.add_argument("--tuning", default=None, help="tuning JSON written by the autotuner (default: the packaged one)")
     ap.add_argument("--placement-ops", type=int, default=300,
@@ -295,7 +296,7 @@ def main():
     cols = [torch.from_numpy(c).to(dev) for c in cols_np]
     bk, bp = torch.from_numpy(bk_np).to(dev), torch.from_numpy(bp_np).to(dev)
 
-    small = run_small(args, torch, lms, datagen, dev)
+    small = None if args.no_small else run_small(args, torch, lms, datagen, dev)
     batched = None
     if not args.no_batched:
         batched = run_batched(args, torch, lms, datagen, cols, dev)

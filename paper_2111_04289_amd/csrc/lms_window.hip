@@ -608,7 +608,8 @@ __global__ __launch_bounds__(kStTPB) void k_wa_scatter_st(WinArgs a) {
   uint32_t* const cur = (uint32_t*)st_lds;          // np: next slot of each partition
   uint32_t* const gof = cur + np;                    // np: staging index of slot 0's partition segment
   uint16_t* const spart = (uint16_t*)(gof + np);     // cap: partition of each staged record
-  char* const stage = (char*)align_up((size_t)(spart + cap), 16);
+  // offsets from the LDS base, so the compiler keeps the stage's address space
+  char* const stage = st_lds + align_up((size_t)((char*)(spart + cap) - st_lds), 16);
   for (int p = threadIdx.x; p < np; p += kStTPB) cur[p] = a.H[(size_t)p * a.g1 + w];
   __syncthreads();
   const uint32_t total = block_scan_array<kStTPB>(cur, np, scratch);  // cur = first slot of each partition
@@ -928,7 +929,11 @@ __device__ __forceinline__ bool insert(const WinArgs& a, Lds& s, const Elem<MA>&
 // L2 (measured: the step 2.6 % faster, the merge 6 %).
 template <class T>
 __device__ __forceinline__ void out_store(T* p, T v) {
-  __builtin_nontemporal_store(v, p);
+  // the output pointers come from an LDS table, so the compiler cannot tell
+  // their address space: marked global, the stores are global stores, which
+  // count only against the vector-memory wait counter (a flat store also
+  // counts against the LDS one, so every later LDS wait would wait for it)
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T*)p);
 }
 
 __device__ __forceinline__ int64_t key_of(const WinArgs& a, const Lds& s, uint32_t kid) {

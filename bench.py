@@ -426,7 +426,8 @@ def main():
         ks = {k: v for k, v in trace.items() if k.startswith(prefix)}
         if ks:
             ms = sum(v[1] for v in ks.values()) / args.steps
-            ops[name] = {"ms": round(ms, 4), "alg_bytes": b, "GB_s": round(b / (ms / 1e3) / 1e9, 1),
+            ops[name] = {"ms": round(ms, 4), "Mrows_s": round(n / ms / 1e3, 1), "alg_bytes": b,
+                         "GB_s": round(b / (ms / 1e3) / 1e9, 1),
                          "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in ks.items()}}
     for k, v in sorted(trace.items(), key=lambda kv: -kv[1][1]):
         log(f"{k:14s} launches {v[0]:4d} avg {v[1] / v[0]:.4f} ms  min {v[2]:.4f}  max {v[3]:.4f}")

@@ -315,7 +315,8 @@ int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nbatch, const
 int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lms_stream stream);
 
 /* Tile and schedule parameters of the windowed group-by (process-wide; NULL
- * or 0 fields select the defaults): rows per scan chunk, target rows per
+ * or 0 fields select the defaults): rows per scan chunk (rounded up to a
+ * power of two, at most 65536), target rows per
  * partition, rows per aggregation piece (>= 1024), persistent scan workgroups
  * per CU, and (key, pane) slots of an aggregation workgroup's LDS table (1024
  * or 2048, the default; the smaller table fits two workgroups' LDS in a CU

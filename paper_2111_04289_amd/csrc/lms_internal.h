@@ -32,16 +32,24 @@ struct Query {
   int64_t nrows;
 };
 
+// p, which points to global memory, typed as a global pointer: accesses
+// through a pointer the compiler cannot place (one read from LDS, say) are
+// otherwise flat instructions, which also count against the LDS wait counter.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gptr(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ int64_t load_i64(const void* p, int dt, int64_t i) {
-  return dt == LMS_I32 ? (int64_t)((const int32_t*)p)[i] : ((const int64_t*)p)[i];
+  return dt == LMS_I32 ? (int64_t)gptr((const int32_t*)p)[i] : gptr((const int64_t*)p)[i];
 }
 
 __device__ __forceinline__ double load_f64(const void* p, int dt, int64_t i) {
   switch (dt) {
-    case LMS_I32: return (double)((const int32_t*)p)[i];
-    case LMS_I64: return (double)((const int64_t*)p)[i];
-    case LMS_F32: return (double)((const float*)p)[i];
-    default: return ((const double*)p)[i];
+    case LMS_I32: return (double)gptr((const int32_t*)p)[i];
+    case LMS_I64: return (double)gptr((const int64_t*)p)[i];
+    case LMS_F32: return (double)gptr((const float*)p)[i];
+    default: return gptr((const double*)p)[i];
   }
 }
 
@@ -83,13 +91,13 @@ __device__ __forceinline__ void load_i64_rows(const void* p, int dt, const int64
   if (dt == LMS_I32) {
     int32_t x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = ((const int32_t*)p)[ld[u] ? idx[u] : safe];
+    for (int u = 0; u < U; ++u) x[u] = gptr((const int32_t*)p)[ld[u] ? idx[u] : safe];
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = ld[u] ? (int64_t)x[u] : 0;
   } else {
     int64_t x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = ((const int64_t*)p)[ld[u] ? idx[u] : safe];
+    for (int u = 0; u < U; ++u) x[u] = gptr((const int64_t*)p)[ld[u] ? idx[u] : safe];
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = ld[u] ? x[u] : 0;
   }
@@ -102,7 +110,7 @@ __device__ __forceinline__ void load_f64_rows(const void* p, int dt, const int64
     case LMS_F32: {
       float x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = ((const float*)p)[ld[u] ? idx[u] : safe];
+      for (int u = 0; u < U; ++u) x[u] = gptr((const float*)p)[ld[u] ? idx[u] : safe];
 #pragma unroll
       for (int u = 0; u < U; ++u) v[u] = ld[u] ? (double)x[u] : 0.0;
       break;
@@ -110,7 +118,7 @@ __device__ __forceinline__ void load_f64_rows(const void* p, int dt, const int64
     case LMS_F64: {
       double x[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) x[u] = ((const double*)p)[ld[u] ? idx[u] : safe];
+      for (int u = 0; u < U; ++u) x[u] = gptr((const double*)p)[ld[u] ? idx[u] : safe];
 #pragma unroll
       for (int u = 0; u < U; ++u) v[u] = ld[u] ? x[u] : 0.0;
       break;
@@ -160,15 +168,18 @@ __device__ __forceinline__ bool wide_dtype(int dt) { return dt == LMS_I64 || dt 
 // template parameter, so a caller branches on it once around the loads and
 // their uses: a width branch joining between a load and its first use would
 // make the wave wait for each load before issuing the next.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef uint64_t u64x2_t __attribute__((ext_vector_type(2)));
+
 template <bool kWide, int U>
 __device__ __forceinline__ void load_quads(const void* col, const int64_t (&r0)[U], uint64_t (&v)[U][4]) {
   if constexpr (kWide) {
-    ulonglong2 x[U], y[U];
+    u64x2_t x[U], y[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const uint64_t* q = (const uint64_t*)col + r0[u];
-      x[u] = *(const ulonglong2*)q;
-      y[u] = *(const ulonglong2*)(q + 2);
+      x[u] = *gptr((const u64x2_t*)q);
+      y[u] = *gptr((const u64x2_t*)(q + 2));
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -178,9 +189,9 @@ __device__ __forceinline__ void load_quads(const void* col, const int64_t (&r0)[
       v[u][3] = y[u].y;
     }
   } else {
-    uint4 x[U];
+    u32x4_t x[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) x[u] = *(const uint4*)((const uint32_t*)col + r0[u]);
+    for (int u = 0; u < U; ++u) x[u] = *gptr((const u32x4_t*)((const uint32_t*)col + r0[u]));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       v[u][0] = x[u].x;

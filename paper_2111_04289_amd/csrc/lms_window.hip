@@ -46,6 +46,7 @@ constexpr int kLdsLimit = 160 * 1024;
 constexpr int kStackCap = 80;
 constexpr int kUnroll = 4;
 constexpr int kHistUnroll = 8;
+constexpr int64_t kMaxChunk = 65536;  // rows of a scan chunk at most (its pass mask is staged in LDS)
 constexpr int kXcds = 8;  // XCDs of an MI355X
 
 struct Item {
@@ -89,6 +90,7 @@ struct WinArgs {
   PartInfo* pinfo;
   Item* items;
   uint32_t* pfill;  // nparts: partial records reserved so far in each split partition
+  uint64_t* pmask;  // (nrows + 63) / 64: which rows pass the predicates (bit r % 64 of word r / 64)
   // staged rows, one record of `rec` bytes per passing row: key (8 B) at 0,
   // 8-byte values, pane (4 B) at pane_off, 4-byte values, padding to 8 B --
   // one contiguous record keeps a partition's short per-chunk segment to one
@@ -197,6 +199,25 @@ __device__ __forceinline__ uint32_t xcd_chunk(uint32_t g, uint32_t n) {
 
 constexpr int kHistQuads = 4;  // quads per thread per step of the histogram
 
+// Pass bits of the rows [g, g + 256) of a wave's quads (lane l holds rows
+// g + 4l .. g + 4l + 3 in the low four bits of m; g relative to the chunk):
+// each group of 16 lanes ORs its nibbles into one 64-bit word of the chunk's
+// LDS mask, written by its first lane.
+__device__ __forceinline__ void put_quad_mask(uint64_t* lmask, int64_t g, uint32_t m) {
+  const int lane = threadIdx.x & 63;
+  uint64_t v = (uint64_t)(m & 0xFu) << (4 * (lane & 15));
+#pragma unroll
+  for (int d = 1; d < 16; d <<= 1) v |= (uint64_t)__shfl_xor((long long)v, d, 64);
+  if ((lane & 15) == 0) lmask[(g >> 6) + (lane >> 4)] = v;
+}
+
+// LDS bytes of the histogram kernels: the partition counts, then the pass
+// mask of one chunk (written to the workspace once per chunk, so the row
+// loop's waits are not held up by stores).
+__host__ __device__ inline size_t hist_lds(int nparts, int64_t chunk) {
+  return (size_t)((nparts + 1) & ~1) * 4 + (size_t)(chunk + 63) / 64 * 8;
+}
+
 template <bool kWide>
 __device__ __forceinline__ void hist_quads(const WinArgs& a, const void* kc, const int64_t (&kr)[kHistQuads],
                                            const uint32_t (&m)[kHistQuads], uint32_t* hist) {
@@ -214,6 +235,7 @@ __device__ __forceinline__ void hist_quads(const WinArgs& a, const void* kc, con
 
 // LDS histogram of the passing rows of chunk w over the partitions.
 __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
+  uint64_t* const lmask = (uint64_t*)(hist + ((a.nparts + 1) & ~1));  // the chunk's pass words
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) hist[p] = 0;
   __syncthreads();
   const int64_t lo = (int64_t)w * a.chunk;
@@ -232,23 +254,37 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
       for (int u = 0; u < kHistQuads; ++u) r0[u] = b0 + u * 1024 + 4 * threadIdx.x;
       quads_pass<kHistQuads>(a.q, r0, m);
 #pragma unroll
+      for (int u = 0; u < kHistQuads; ++u) put_quad_mask(lmask, b0 - lo + u * 1024 + (threadIdx.x & ~63u) * 4, m[u]);
+#pragma unroll
       for (int u = 0; u < kHistQuads; ++u) kr[u] = m[u] ? r0[u] : lo;
       if (wide_dtype(kdt)) hist_quads<true>(a, kc, kr, m, hist);
       else hist_quads<false>(a, kc, kr, m, hist);
     }
   }
-  // kHistUnroll rows per thread per step; keys are loaded only for passing
-  // rows, so a selective predicate leaves most key lines unread
-  for (int64_t b = b0 + threadIdx.x; b < hi; b += (int64_t)kScanTPB * kHistUnroll) {
+  // kHistUnroll rows per thread per step, a wave taking 64 kHistUnroll
+  // consecutive rows (64 per load, from a multiple of 64); keys are loaded only
+  // for passing rows, so a selective predicate leaves most key lines unread
+  const int lane = threadIdx.x & 63;
+  for (int64_t b = b0 + (threadIdx.x >> 6) * (64 * kHistUnroll) + lane; b < hi;
+       b += (int64_t)kScanTPB * kHistUnroll) {
     bool ok[kHistUnroll];
     int64_t key[kHistUnroll];
     int64_t idx[kHistUnroll];
 #pragma unroll
     for (int u = 0; u < kHistUnroll; ++u) {
-      idx[u] = b + (int64_t)u * kScanTPB;
+      idx[u] = b + (int64_t)u * 64;
       ok[u] = idx[u] < hi;
     }
     rows_pass<kHistUnroll>(a.q, idx, ok, lo);
+    // the wave's kHistUnroll pass words are consecutive: lane u holds word u
+    uint64_t mw = 0;
+#pragma unroll
+    for (int u = 0; u < kHistUnroll; ++u) {
+      const uint64_t bits = __ballot(ok[u]);
+      if (lane == u) mw = bits;
+    }
+    const int64_t wrow = b - lane + (int64_t)lane * 64;  // first row of word `lane`
+    if (lane < kHistUnroll && wrow < hi) lmask[(wrow - lo) >> 6] = mw;
     load_i64_rows<kHistUnroll>(kc, kdt, idx, ok, lo, key);
 #pragma unroll
     for (int u = 0; u < kHistUnroll; ++u)
@@ -256,6 +292,8 @@ __device__ void hist_chunk(const WinArgs& a, uint32_t w, uint32_t* hist) {
   }
   __syncthreads();
   for (int p = threadIdx.x; p < a.nparts; p += kScanTPB) a.H[(size_t)p * a.g1 + w] = hist[p];
+  const int nw = (int)((hi - lo + 63) >> 6);
+  for (int i = threadIdx.x; i < nw; i += kScanTPB) gptr(a.pmask)[(lo >> 6) + i] = lmask[i];
   __syncthreads();
 }
 
@@ -537,7 +575,18 @@ __device__ void scatter_rows(const WinArgs& a, uint32_t w, Sink sink) {
       idx[u] = b + (int64_t)u * TPB;
       ok[u] = idx[u] < hi;
     }
-    rows_pass<kU>(a.q, idx, ok, lo);
+    // the histogram pass recorded which rows pass; a wave whose rows of this
+    // step all fail skips their loads
+    uint64_t wd[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) wd[u] = gptr(a.pmask)[(ok[u] ? idx[u] : lo) >> 6];
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      ok[u] = ok[u] && ((wd[u] >> (idx[u] & 63)) & 1u);
+      any |= ok[u];
+    }
+    if (!__ballot(any)) continue;
     load_i64_rows<kU>(kc, kdt, idx, ok, lo, key);
     load_i64_rows<kU>(tc, tdt, idx, ok, lo, ts);
 #pragma unroll
@@ -933,7 +982,7 @@ __device__ __forceinline__ void out_store(T* p, T v) {
   // their address space: marked global, the stores are global stores, which
   // count only against the vector-memory wait counter (a flat store also
   // counts against the LDS one, so every later LDS wait would wait for it)
-  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) T*)p);
+  __builtin_nontemporal_store(v, gptr(p));
 }
 
 __device__ __forceinline__ int64_t key_of(const WinArgs& a, const Lds& s, uint32_t kid) {
@@ -1938,8 +1987,8 @@ int acc_bound(int nacc) { return nacc <= 2 ? 2 : nacc <= 4 ? 4 : nacc <= 6 ? 6 :
 Plan make_plan(int64_t n, int nval, int nacc) {
   Plan p{};
   p.n = n;
-  if (g_tuning.chunk_rows > 0) p.chunk = next_pow2(g_tuning.chunk_rows);
-  else p.chunk = std::min<int64_t>(65536, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
+  if (g_tuning.chunk_rows > 0) p.chunk = std::min<int64_t>(kMaxChunk, next_pow2(g_tuning.chunk_rows));
+  else p.chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
   p.g1 = (int)((n + p.chunk - 1) / p.chunk);
   // the LDS group table sets the scale: by default a partition targets 8 rows
   // per table slot and an aggregation piece 4 (16384 and 8192 at 2048 slots)
@@ -1972,6 +2021,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   PartInfo* pinfo = c.take<PartInfo>(p.nparts);
   Item* items = c.take<Item>(p.max_items);
   uint32_t* pfill = c.take<uint32_t>(p.nparts);
+  uint64_t* pmask = c.take<uint64_t>((size_t)(p.n + 63) / 64 + 1);
   char* srec = c.take<char>((size_t)p.n * rec_bound(p.nval) + 8);  // + a word read past the last record
   int64_t* pkey = c.take<int64_t>(p.n);
   uint32_t* ppane = c.take<uint32_t>(p.n);
@@ -1988,6 +2038,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
     a->pinfo = pinfo;
     a->items = items;
     a->pfill = pfill;
+    a->pmask = pmask;
     a->srec = srec;
     a->pkey = pkey;
     a->ppane = ppane;
@@ -2220,7 +2271,8 @@ int launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
   const size_t plds = (size_t)c.max_nparts * 4;
   const MultiLim lim{(uint32_t)c.max_nparts, (uint32_t)c.agg_lds, (uint32_t)MA, 0};
   LMS_LAUNCH("k_wam_init", k_wam_init, dim3(4), dim3(256), 0, st, desc, lim);
-  LMS_LAUNCH("k_wam_hist", k_wam_hist, dim3(c.grid_scan), dim3(kScanTPB), plds, st, desc, lim);
+  LMS_LAUNCH("k_wam_hist", k_wam_hist, dim3(c.grid_scan), dim3(kScanTPB), hist_lds(c.max_nparts, kMaxChunk), st,
+             desc, lim);
   LMS_LAUNCH("k_wam_scan1", k_wam_scan1, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scanp", k_wam_scanp, dim3(c.grid_scan), dim3(kPlanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scan2", k_wam_scan2, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
@@ -2245,7 +2297,7 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
   if (in->nrows == 0) LMS_LAUNCH("k_wa_init", k_wa_init, dim3(1), dim3(64), 0, st, a);
   if (in->nrows > 0) {
     const size_t plds = (size_t)p.nparts * 4;
-    LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(xcd_slots(p.g1)), dim3(kScanTPB), plds, st, a);
+    LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(xcd_slots(p.g1)), dim3(kScanTPB), hist_lds(p.nparts, p.chunk), st, a);
     LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kPlanTPB), 0, st, a);
     LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);

@@ -555,7 +555,7 @@ __device__ __forceinline__ void put_record(const WinArgs& a, char* r, int64_t ke
 // shared row in their place, so a selective predicate leaves most lines
 // unread.
 template <int MA, int TPB, class Sink>
-__device__ void scatter_rows(const WinArgs& a, uint32_t w, Sink sink) {
+__device__ void scatter_rows(const WinArgs& a, uint32_t w, uint64_t* lmask, Sink sink) {
   // eight value columns per row would hold too many loads in registers at 4 rows
   constexpr int kU = MA <= 6 ? kUnroll : 2;
   const int64_t b0 = a.hdr[0];
@@ -566,6 +566,11 @@ __device__ void scatter_rows(const WinArgs& a, uint32_t w, Sink sink) {
   const void* tc = a.q.col[a.ts_col];
   const int tdt = a.q.dt[a.ts_col];
   bool range_err = false;
+  // the chunk's pass words, staged in LDS (lmask: chunk / 64 words): a step
+  // whose rows all fail then costs one LDS read instead of a memory round trip
+  const int nw = (int)((hi - lo + 63) >> 6);
+  for (int i = threadIdx.x; i < nw; i += TPB) lmask[i] = gptr(a.pmask)[(lo >> 6) + i];
+  __syncthreads();
   for (int64_t b = lo + threadIdx.x; b < hi; b += (int64_t)TPB * kU) {
     bool ok[kU];
     int64_t key[kU], ts[kU], idx[kU];
@@ -579,7 +584,7 @@ __device__ void scatter_rows(const WinArgs& a, uint32_t w, Sink sink) {
     // step all fail skips their loads
     uint64_t wd[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) wd[u] = gptr(a.pmask)[(ok[u] ? idx[u] : lo) >> 6];
+    for (int u = 0; u < kU; ++u) wd[u] = lmask[((ok[u] ? idx[u] : lo) - lo) >> 6];
     bool any = false;
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
@@ -623,9 +628,10 @@ __device__ void scatter_rows(const WinArgs& a, uint32_t w, Sink sink) {
 // the next slot of its partition's segment for this chunk.
 template <int MA>
 __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
+  uint64_t* const lmask = (uint64_t*)(cursor + ((a.nparts + 1) & ~1));  // LDS of hist_lds(nparts, chunk)
   for (int p = threadIdx.x; p < a.nparts; p += kScatterTPB) cursor[p] = a.Off[(size_t)p * a.g1 + w];
   __syncthreads();
-  scatter_rows<MA, kScatterTPB>(a, w, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
+  scatter_rows<MA, kScatterTPB>(a, w, lmask, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
     const uint32_t pos = atomicAdd(&cursor[part], 1u);
     put_record<MA>(a, a.srec + (size_t)pos * a.rec, key, qp, val);
   });
@@ -642,8 +648,8 @@ __device__ void scatter_chunk(const WinArgs& a, uint32_t w, uint32_t* cursor) {
 constexpr int kStTPB = 1024;
 constexpr size_t kStLds = 160 * 1024 - 512;  // dynamic LDS of the staged scatter
 
-__host__ __device__ inline uint32_t stage_cap(int nparts, int rec) {
-  return (uint32_t)((kStLds - 16 - 8 * (size_t)nparts) / (size_t)(rec + 2));
+__host__ __device__ inline uint32_t stage_cap(int nparts, int rec, int64_t chunk) {
+  return (uint32_t)((kStLds - 16 - 8 * (size_t)nparts - 8 - (size_t)(chunk + 63) / 64 * 8) / (size_t)(rec + 2));
 }
 
 template <int MA>
@@ -653,10 +659,11 @@ __global__ __launch_bounds__(kStTPB) void k_wa_scatter_st(WinArgs a) {
   const uint32_t w = xcd_chunk(blockIdx.x, (uint32_t)a.g1);
   if (w >= (uint32_t)a.g1) return;
   const int np = a.nparts;
-  const uint32_t cap = stage_cap(np, a.rec);
+  const uint32_t cap = stage_cap(np, a.rec, a.chunk);
   uint32_t* const cur = (uint32_t*)st_lds;          // np: next slot of each partition
   uint32_t* const gof = cur + np;                    // np: staging index of slot 0's partition segment
-  uint16_t* const spart = (uint16_t*)(gof + np);     // cap: partition of each staged record
+  uint64_t* const lmask = (uint64_t*)(st_lds + align_up(8 * (size_t)np, 8));  // chunk / 64 pass words
+  uint16_t* const spart = (uint16_t*)(lmask + (a.chunk + 63) / 64);  // cap: partition of each staged record
   // offsets from the LDS base, so the compiler keeps the stage's address space
   char* const stage = st_lds + align_up((size_t)((char*)(spart + cap) - st_lds), 16);
   for (int p = threadIdx.x; p < np; p += kStTPB) cur[p] = a.H[(size_t)p * a.g1 + w];
@@ -665,7 +672,7 @@ __global__ __launch_bounds__(kStTPB) void k_wa_scatter_st(WinArgs a) {
   if (total > cap) {  // does not fit the stage: straight to the segments
     for (int p = threadIdx.x; p < np; p += kStTPB) cur[p] = a.Off[(size_t)p * a.g1 + w];
     __syncthreads();
-    scatter_rows<MA, kStTPB>(a, w, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
+    scatter_rows<MA, kStTPB>(a, w, lmask, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
       const uint32_t pos = atomicAdd(&cur[part], 1u);
       put_record<MA>(a, a.srec + (size_t)pos * a.rec, key, qp, val);
     });
@@ -673,7 +680,7 @@ __global__ __launch_bounds__(kStTPB) void k_wa_scatter_st(WinArgs a) {
   }
   for (int p = threadIdx.x; p < np; p += kStTPB) gof[p] = a.Off[(size_t)p * a.g1 + w] - cur[p];
   __syncthreads();
-  scatter_rows<MA, kStTPB>(a, w, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
+  scatter_rows<MA, kStTPB>(a, w, lmask, [&](int part, int64_t key, uint64_t qp, const uint64_t(&val)[MA]) {
     const uint32_t slot = atomicAdd(&cur[part], 1u);
     spart[slot] = (uint16_t)part;
     put_record<MA>(a, stage + (size_t)slot * a.rec, key, qp, val);
@@ -2149,7 +2156,8 @@ void launch_tail(const Plan& p, const WinArgs& a, size_t plds, hipStream_t st) {
     if (st_rc) return;
     LMS_LAUNCH("k_wa_scatter", k_wa_scatter_st<MA>, dim3(xcd_slots(p.g1)), dim3(kStTPB), kStLds, st, a);
   } else {
-    LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScatterTPB), plds, st, a);
+    LMS_LAUNCH("k_wa_scatter", k_wa_scatter<MA>, dim3(xcd_slots(p.g1)), dim3(kScatterTPB),
+               hist_lds(p.nparts, p.chunk), st, a);
   }
   LMS_LAUNCH("k_wa_agg", k_wa_agg<MA>, dim3(std::min(p.max_items, resident)), dim3(kAggTPB), p.lds, st, a);
   LMS_LAUNCH("k_wa_merge", k_wa_merge<MA>, dim3(std::min(p.nparts, resident)), dim3(kAggTPB), p.lds, st, a);
@@ -2276,7 +2284,8 @@ int launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
   LMS_LAUNCH("k_wam_scan1", k_wam_scan1, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scanp", k_wam_scanp, dim3(c.grid_scan), dim3(kPlanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scan2", k_wam_scan2, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
-  LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScatterTPB), plds, st, desc, lim);
+  LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScatterTPB), hist_lds(c.max_nparts, kMaxChunk),
+             st, desc, lim);
   LMS_LAUNCH("k_wam_agg", k_wam_agg<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
   LMS_LAUNCH("k_wam_merge", k_wam_merge<MA>, dim3(c.grid_agg), dim3(kAggTPB), (size_t)c.agg_lds, st, desc, lim);
   return LMS_OK;

@@ -1427,34 +1427,38 @@ __device__ void aggregate_and_emit(const WinArgs& a, Lds& s, const Segments& sg,
     bool ovf = false;
     {
       const uint32_t lo = sg.lo, hi = sg.hi;
-      Elem<MA> cur;
-      if (lo + threadIdx.x < hi) {
-        if (sg.partial) load_partial<MA>(a, lo + threadIdx.x, cur);
-        else load_row<MA>(a, lo + threadIdx.x, cur);
-      }
-      for (uint32_t b = lo; b < hi; b += kAggTPB) {
-        const uint32_t e = b + threadIdx.x;
-        // This round's element is converted before the next round's loads are
-        // issued, and inserted while they are in flight: a conversion after
-        // them waits on every outstanding load (the wait counter is in issue
-        // order), which would leave no load in flight during the insertion.
-        bool ins = false;
-        uint64_t h = 0;
-        if (e < hi) {
-          if (!sg.partial) finish_row<MA>(a, cur);
-          h = fmix64((uint64_t)cur.key);
-          const uint32_t sh = subhash(h);
-          const int64_t q = (int64_t)cur.pane;
-          ins = sh >= rlo && sh < rhi && q >= ilo && q < ihi;
+      // two elements per thread per round, both loads issued before either
+      // is used: the round waits once for two loads
+      for (uint32_t b = lo; b < hi; b += 2 * kAggTPB) {
+        const uint32_t e0 = b + threadIdx.x, e1 = e0 + kAggTPB;
+        Elem<MA> x0, x1;
+        if (e0 < hi) {
+          if (sg.partial) load_partial<MA>(a, e0, x0);
+          else load_row<MA>(a, e0, x0);
         }
-        settle<MA>(cur);  // on every path, so no path reaches the insertion with a pending load
-        Elem<MA> nxt;
-        if (e + kAggTPB < hi) {
-          if (sg.partial) load_partial<MA>(a, e + kAggTPB, nxt);
-          else load_row<MA>(a, e + kAggTPB, nxt);
+        if (e1 < hi) {
+          if (sg.partial) load_partial<MA>(a, e1, x1);
+          else load_row<MA>(a, e1, x1);
         }
-        if (ins && !insert<MA>(a, s, cur, h)) s.misc[M_OVF] = 1;
-        cur = nxt;
+        bool ins0 = false, ins1 = false;
+        uint64_t h0 = 0, h1 = 0;
+        if (e0 < hi) {
+          if (!sg.partial) finish_row<MA>(a, x0);
+          h0 = fmix64((uint64_t)x0.key);
+          const uint32_t sh = subhash(h0);
+          const int64_t q = (int64_t)x0.pane;
+          ins0 = sh >= rlo && sh < rhi && q >= ilo && q < ihi;
+        }
+        if (e1 < hi) {
+          if (!sg.partial) finish_row<MA>(a, x1);
+          h1 = fmix64((uint64_t)x1.key);
+          const uint32_t sh = subhash(h1);
+          const int64_t q = (int64_t)x1.pane;
+          ins1 = sh >= rlo && sh < rhi && q >= ilo && q < ihi;
+        }
+        bool fail = ins0 && !insert<MA>(a, s, x0, h0);
+        fail = (ins1 && !insert<MA>(a, s, x1, h1)) || fail;
+        if (fail) s.misc[M_OVF] = 1;
         __syncthreads();
         const bool o = s.misc[M_OVF] != 0;
         __syncthreads();  // every thread has read the flag before the next round may set it

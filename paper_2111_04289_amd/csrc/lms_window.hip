@@ -1275,30 +1275,38 @@ __device__ void emit_sliding(const WinArgs& a, Lds& s, int64_t b0, int64_t wmin,
     __syncthreads();
   }
   // Permute the group arrays (id, count, accumulators) into the sorted order,
-  // one array at a time through registers, so the composition below reads a
-  // key's consecutive panes from consecutive slots instead of through the slot
-  // index.
+  // all of them in one pass through registers (one pair of barriers), so the
+  // composition below reads a key's consecutive panes from consecutive slots
+  // instead of through the slot index.
   {
     constexpr int kPer = 2048 / kAggTPB;  // eg <= 2048
-    auto permute = [&](auto* arr) {
-      using T = typename std::remove_pointer<decltype(arr)>::type;
-      T v[kPer];
+    uint64_t vg[kPer], va[kPer][MA];
+    uint32_t vc[kPer];
 #pragma unroll
-      for (int t = 0; t < kPer; ++t) {
-        const uint32_t i = threadIdx.x + t * kAggTPB;
-        if (i < ng) v[t] = arr[(uint32_t)s.sorted[i]];
-      }
-      __syncthreads();
+    for (int t = 0; t < kPer; ++t) {
+      const uint32_t i = threadIdx.x + t * kAggTPB;
+      if (i < ng) {
+        const uint32_t src = (uint32_t)s.sorted[i];
+        vg[t] = s.gid[src];
+        vc[t] = s.gcnt[src];
 #pragma unroll
-      for (int t = 0; t < kPer; ++t) {
-        const uint32_t i = threadIdx.x + t * kAggTPB;
-        if (i < ng) arr[i] = v[t];
+        for (int k = 0; k < MA; ++k)
+          if (k < a.nacc) va[t][k] = s.acc[(size_t)k * a.eg + src];
       }
-      __syncthreads();
-    };
-    permute(s.gid);
-    permute(s.gcnt);
-    for (int k = 0; k < a.nacc; ++k) permute(s.acc + (size_t)k * a.eg);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const uint32_t i = threadIdx.x + t * kAggTPB;
+      if (i < ng) {
+        s.gid[i] = vg[t];
+        s.gcnt[i] = vc[t];
+#pragma unroll
+        for (int k = 0; k < MA; ++k)
+          if (k < a.nacc) s.acc[(size_t)k * a.eg + i] = va[t][k];
+      }
+    }
+    __syncthreads();
   }
   for (uint32_t i = threadIdx.x; i < ng; i += kAggTPB) {
     const uint64_t v = s.sorted[i];

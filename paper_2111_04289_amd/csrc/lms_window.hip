@@ -1776,7 +1776,7 @@ __global__ void k_wam_init(const char* desc, MultiLim lim) {
   }
 }
 
-__global__ __launch_bounds__(kScanTPB) void k_wam_hist(const char* desc, MultiLim lim) {
+__global__ __launch_bounds__(kScanTPB, 5) void k_wam_hist(const char* desc, MultiLim lim) {
   extern __shared__ uint32_t hist[];
   __shared__ WinArgs sa;
   const MultiView v = multi_view(desc);

@@ -1727,6 +1727,8 @@ struct MultiView {
   const uint32_t* cpre;  // nb + 1 chunk prefix
   const uint32_t* ppre;  // nb + 1 partition prefix
   const uint32_t* ipre;  // nb + 1 item-slot prefix
+  uint32_t* rpre;        // nb + 1 prefix of the batches' planned items (set by k_wam_real)
+  uint32_t* spre;        // nb + 1 prefix of the batches' split partitions (set by k_wam_real)
   const WinArgs* args;   // nb
 };
 
@@ -1740,6 +1742,10 @@ __device__ __forceinline__ MultiView multi_view(const char* desc) {
   v.ppre = (const uint32_t*)(desc + o);
   o += align_up((size_t)(nb + 1) * 4, 16);
   v.ipre = (const uint32_t*)(desc + o);
+  o += align_up((size_t)(nb + 1) * 4, 16);
+  v.rpre = (uint32_t*)(desc + o);
+  o += align_up((size_t)(nb + 1) * 4, 16);
+  v.spre = (uint32_t*)(desc + o);
   o += align_up((size_t)(nb + 1) * 4, 16);
   v.args = (const WinArgs*)(desc + align_up(o, 16));
   return v;
@@ -1832,6 +1838,40 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scan2(const char* desc, MultiL
   }
 }
 
+// Prefixes of the batches' planned items and split partitions (after the
+// planner), so the aggregation and merge stages visit only real work.  One
+// workgroup; each thread sums a run of consecutive batches.
+__global__ __launch_bounds__(kPlanTPB) void k_wam_real(const char* desc, MultiLim lim) {
+  __shared__ uint32_t si[kPlanTPB], ss[kPlanTPB];
+  __shared__ uint32_t scratch[kPlanTPB / 64 + 1];
+  const MultiView v = multi_view(desc);
+  if (!multi_fits(v.hdr, lim)) return;
+  const uint32_t nb = v.hdr->nb;
+  const uint32_t per = (nb + kPlanTPB - 1) / kPlanTPB;
+  const uint32_t b0 = min(nb, threadIdx.x * per), b1 = min(nb, b0 + per);
+  uint32_t ci = 0, cs = 0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    ci += (uint32_t)v.args[b].hdr[1];
+    cs += (uint32_t)v.args[b].hdr[4];
+  }
+  si[threadIdx.x] = ci;
+  ss[threadIdx.x] = cs;
+  __syncthreads();
+  const uint32_t ti = block_scan_array<kPlanTPB>(si, kPlanTPB, scratch);
+  const uint32_t ts = block_scan_array<kPlanTPB>(ss, kPlanTPB, scratch);
+  uint32_t ri = si[threadIdx.x], rs = ss[threadIdx.x];
+  for (uint32_t b = b0; b < b1; ++b) {
+    v.rpre[b] = ri;
+    v.spre[b] = rs;
+    ri += (uint32_t)v.args[b].hdr[1];
+    rs += (uint32_t)v.args[b].hdr[4];
+  }
+  if (threadIdx.x == 0) {
+    v.rpre[nb] = ti;
+    v.spre[nb] = ts;
+  }
+}
+
 template <int MA>
 __global__ __launch_bounds__(kScatterTPB) void k_wam_scatter(const char* desc, MultiLim lim) {
   extern __shared__ uint32_t cursor[];
@@ -1856,12 +1896,12 @@ __global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wam_agg(const char* 
   const MultiView v = multi_view(desc);
   if (!multi_fits(v.hdr, lim)) return;
   uint32_t cur = ~0u;
-  for (uint32_t g = blockIdx.x; g < v.hdr->nitems; g += gridDim.x) {
-    const uint32_t b = batch_of(v.ipre, v.hdr->nb, g);
-    const uint32_t item = g - v.ipre[b];
-    if ((int64_t)item >= v.args[b].hdr[1]) continue;  // slot beyond this batch's items
+  // only the items the planner made (most of each batch's item slots stay empty)
+  const uint32_t nreal = v.rpre[v.hdr->nb];
+  for (uint32_t g = blockIdx.x; g < nreal; g += gridDim.x) {
+    const uint32_t b = batch_of(v.rpre, v.hdr->nb, g);
     load_args(v, b, &sa, &cur);
-    agg_item<MA>(sa, item, lds_raw);
+    agg_item<MA>(sa, g - v.rpre[b], lds_raw);
   }
 }
 
@@ -1872,12 +1912,12 @@ __global__ __launch_bounds__(kAggTPB, agg_waves(MA)) void k_wam_merge(const char
   const MultiView v = multi_view(desc);
   if (!multi_fits(v.hdr, lim)) return;
   uint32_t cur = ~0u;
-  for (uint32_t g = blockIdx.x; g < v.hdr->nparts; g += gridDim.x) {
-    const uint32_t b = batch_of(v.ppre, v.hdr->nb, g);
-    const uint32_t p = g - v.ppre[b];
-    if (v.args[b].pinfo[p].kp <= 1) continue;
+  // only the split partitions, in each batch's claim order
+  const uint32_t nsplit = v.spre[v.hdr->nb];
+  for (uint32_t g = blockIdx.x; g < nsplit; g += gridDim.x) {
+    const uint32_t b = batch_of(v.spre, v.hdr->nb, g);
     load_args(v, b, &sa, &cur);
-    merge_part<MA>(sa, p, lds_raw);
+    merge_part<MA>(sa, sa.splits[g - v.spre[b]], lds_raw);
   }
 }
 
@@ -2273,7 +2313,7 @@ struct DescStage {
 DescStage g_stage;
 
 size_t multi_desc_bytes(int nb) {
-  size_t o = sizeof(MultiHdr) + 3 * align_up((size_t)(nb + 1) * 4, 16);
+  size_t o = sizeof(MultiHdr) + 5 * align_up((size_t)(nb + 1) * 4, 16);
   return align_up(align_up(o, 16) + (size_t)nb * sizeof(WinArgs), 256);
 }
 
@@ -2295,6 +2335,7 @@ int launch_multi(const lms_multi_config& c, const char* desc, hipStream_t st) {
              desc, lim);
   LMS_LAUNCH("k_wam_scan1", k_wam_scan1, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scanp", k_wam_scanp, dim3(c.grid_scan), dim3(kPlanTPB), 0, st, desc, lim);
+  LMS_LAUNCH("k_wam_real", k_wam_real, dim3(1), dim3(kPlanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scan2", k_wam_scan2, dim3(c.grid_scan), dim3(kScanTPB), 0, st, desc, lim);
   LMS_LAUNCH("k_wam_scatter", k_wam_scatter<MA>, dim3(c.grid_scan), dim3(kScatterTPB), hist_lds(c.max_nparts, kMaxChunk),
              st, desc, lim);
@@ -2445,6 +2486,7 @@ extern "C" int lms_window_agg_multi_prepare(const lms_batch* batches, int32_t nb
   o += align_up((size_t)(nbatch + 1) * 4, 16);
   uint32_t* ipre = (uint32_t*)(hbuf + o);
   o += align_up((size_t)(nbatch + 1) * 4, 16);
+  o += 2 * align_up((size_t)(nbatch + 1) * 4, 16);  // item and split prefixes, set on the device
   WinArgs* args = (WinArgs*)(hbuf + align_up(o, 16));
   size_t off = dbytes;
   int max_nparts = 1, max_nacc = 0;

@@ -1804,8 +1804,13 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scan1(const char* desc, MultiL
   const MultiView v = multi_view(desc);
   if (!multi_fits(v.hdr, lim)) return;
   uint32_t cur = ~0u;
-  for (uint32_t g = blockIdx.x; g < v.hdr->nparts; g += gridDim.x) {
-    const uint32_t b = batch_of(v.ppre, v.hdr->nb, g);
+  // a contiguous run of partitions per workgroup: the batch (and its argument
+  // copy) changes only at batch boundaries
+  const uint32_t n = v.hdr->nparts, per = (n + gridDim.x - 1) / gridDim.x;
+  const uint32_t g0 = min(n, blockIdx.x * per), g1 = min(n, g0 + per);
+  uint32_t b = g0 < g1 ? batch_of(v.ppre, v.hdr->nb, g0) : 0;
+  for (uint32_t g = g0; g < g1; ++g) {
+    while (g >= v.ppre[b + 1]) ++b;
     load_args(v, b, &sa, &cur);
     scan1_part(sa, (int)(g - v.ppre[b]), scratch);
     __syncthreads();
@@ -1831,8 +1836,11 @@ __global__ __launch_bounds__(kScanTPB) void k_wam_scan2(const char* desc, MultiL
   const MultiView v = multi_view(desc);
   if (!multi_fits(v.hdr, lim)) return;
   uint32_t cur = ~0u;
-  for (uint32_t g = blockIdx.x; g < v.hdr->nparts; g += gridDim.x) {
-    const uint32_t b = batch_of(v.ppre, v.hdr->nb, g);
+  const uint32_t n = v.hdr->nparts, per = (n + gridDim.x - 1) / gridDim.x;  // as in k_wam_scan1
+  const uint32_t g0 = min(n, blockIdx.x * per), g1 = min(n, g0 + per);
+  uint32_t b = g0 < g1 ? batch_of(v.ppre, v.hdr->nb, g0) : 0;
+  for (uint32_t g = g0; g < g1; ++g) {
+    while (g >= v.ppre[b + 1]) ++b;
     load_args(v, b, &sa, &cur);
     scan2_part(sa, (int)(g - v.ppre[b]), scratch);
   }

@@ -120,7 +120,7 @@ def run_batched(args, torch, lms, datagen, cols, dev):
     pool_n = int(cols[0].shape[0])
     hi = min(8 << 20, pool_n)
     sizes = np.exp(rng.uniform(np.log(1024), np.log(hi), args.batches)).astype(np.int64)
-    offs = [int(rng.integers(0, pool_n - s + 1)) for s in sizes]
+    offs = [4 * int(rng.integers(0, (pool_n - s) // 4 + 1)) for s in sizes]  # 16-byte aligned, as separate buffers
     batches = [[c[o:o + int(s)] for c in cols] for o, s in zip(offs, sizes)]
     total = int(sizes.sum())
     preds, projs = [(2, lms.LT, 500)], [(2, 2, 0)]

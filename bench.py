@@ -108,7 +108,19 @@ def run_serving(args, log):
     return out
 
 
-def run_batched(args, torch, lms, datagen, cols, dev):
+def batched_alg_bytes(val_np, offs, sizes, groups):
+    """Algorithmic bytes of the batched query: the predicate column (4 B) of
+    every row, the 128-byte lines of the two 8-byte columns (ts, key) that
+    hold at least one passing row, and the result (key, window start, COUNT,
+    SUM: 32 B per group)."""
+    lines = 0
+    for o, n in zip(offs, sizes):
+        rows = np.flatnonzero(val_np[o:o + int(n)] < 500) + o
+        lines += 2 * len(np.unique(rows // 16))  # 16 rows of an 8-byte column per line
+    return 4 * int(np.sum(sizes)) + 128 * lines + 32 * int(groups)
+
+
+def run_batched(args, torch, lms, datagen, cols, dev, val_np=None):
     """256 micro-batches with log-uniform row counts in [1K, 8M], sliced from the
     resident 16M-row pool, through the tumbling-window query (val < 500,
     v2 = val * 2, key x 1 s, COUNT and SUM(v2)): one launch sequence per batch
@@ -206,6 +218,11 @@ def run_batched(args, torch, lms, datagen, cols, dev):
                                     "p99": round(float(np.percentile(lat, 99)), 4),
                                     "max": round(float(lat.max()), 4)},
            "tuning": tuned}
+    if val_np is not None:
+        ab = batched_alg_bytes(val_np, offs, sizes, res["groups"])
+        gbs = ab / (ms_graph / 1e3) / 1e9
+        res["roofline"] = {"alg_bytes": ab, "GB_s": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                           "frac": round(gbs / HBM_PEAK_GBS, 4)}
     log(f"batched {res}")
     del graph, job, mgroups, single_groups
     torch.cuda.synchronize()
@@ -299,7 +316,7 @@ def main():
     small = None if args.no_small else run_small(args, torch, lms, datagen, dev)
     batched = None
     if not args.no_batched:
-        batched = run_batched(args, torch, lms, datagen, cols, dev)
+        batched = run_batched(args, torch, lms, datagen, cols, dev, cols_np[2])
 
     from paper_2111_04289_amd import autotune
     tuned = autotune.apply("sliding", args.tuning)

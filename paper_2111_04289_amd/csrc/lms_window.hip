@@ -834,39 +834,53 @@ struct Elem {
   uint64_t in[MA];  // input of accumulator k (int64 or double bits)
 };
 
-// Issues the loads of staged row e: key, pane and every value as two 4-byte
-// words at its offset whatever its width (for a 4-byte value the second word
-// is the next field, or padding, or the word after the last record), so no
-// load sits under a dtype branch and a prefetch does not wait for itself.
-// finish_row converts the values into accumulator inputs once they are needed.
+// Issues the loads of staged row e as its 8-byte words: a record is 8-byte
+// aligned and at most MA + 2 words long (key, 8-byte values, then the pane and
+// the 4-byte values in pairs), so this is one load per word, however many
+// values it holds.  The words are kept raw in the fields of x in word order
+// (key, pane word, then in[]); finish_row picks the pane and the values out of
+// them once they are needed, so no load waits for another's result.
 template <int MA>
 __device__ __forceinline__ void load_row(const WinArgs& a, uint32_t e, Elem<MA>& x) {
-  const char* const r = a.srec + (size_t)e * a.rec;
-  x.key = *(const int64_t*)r;
-  x.pane = *(const uint32_t*)(r + a.pane_off);
-  x.cnt = 1;
+  const uint64_t* const r = (const uint64_t*)(a.srec + (size_t)e * a.rec);
+  const int nw = a.rec >> 3;
+  uint64_t w[MA + 2];
 #pragma unroll
-  for (int v = 0; v < MA; ++v) {
-    const char* c = r + (v < a.nval ? a.voff[v] : 0);
-    const uint32_t lo = *(const uint32_t*)c, hi = *(const uint32_t*)(c + 4);
-    x.in[v] = ((uint64_t)hi << 32) | lo;
-  }
+  for (int t = 0; t < MA + 2; ++t) w[t] = t < nw ? gptr(r)[t] : 0;
+  x.key = (int64_t)w[0];
+  x.pane = (uint32_t)w[1];
+  x.cnt = (uint32_t)(w[1] >> 32);
+#pragma unroll
+  for (int k = 0; k < MA; ++k) x.in[k] = w[2 + k];
 }
 
-// Staged values (raw words from load_row) -> accumulator inputs: int64, or
-// double bits for float columns and for AVG of an integer column.
+// Raw record words (from load_row) -> pane and accumulator inputs: int64, or
+// double bits for float columns and for AVG of an integer column.  A field's
+// word is read from a vector of the record's words at its word index, which
+// is uniform (a register-indexed move: a plain array indexed at run time would
+// go to private memory).
 template <int MA>
 __device__ __forceinline__ void finish_row(const WinArgs& a, Elem<MA>& x) {
+  typedef uint64_t words_t __attribute__((ext_vector_type(MA + 2)));
+  words_t w;
+  w[0] = (uint64_t)x.key;
+  w[1] = ((uint64_t)x.cnt << 32) | x.pane;
+#pragma unroll
+  for (int k = 0; k < MA; ++k) w[2 + k] = x.in[k];
+  auto word = [&](int t) { return w[t]; };
+  x.pane = (uint32_t)word(a.pane_off >> 3);
+  x.cnt = 1;
   uint64_t raw[MA];
 #pragma unroll
   for (int v = 0; v < MA; ++v) {
-    const uint64_t w = x.in[v];
     raw[v] = 0;
     if (v < a.nval) {
+      const int o = a.voff[v];
+      const uint64_t wv = word(o >> 3) >> ((o & 4) * 8);
       switch (a.vdt[v]) {
-        case LMS_I32: raw[v] = (uint64_t)(int64_t)(int32_t)(uint32_t)w; break;
-        case LMS_F32: raw[v] = (uint64_t)__double_as_longlong((double)__uint_as_float((uint32_t)w)); break;
-        default: raw[v] = w; break;
+        case LMS_I32: raw[v] = (uint64_t)(int64_t)(int32_t)(uint32_t)wv; break;
+        case LMS_F32: raw[v] = (uint64_t)__double_as_longlong((double)__uint_as_float((uint32_t)wv)); break;
+        default: raw[v] = wv; break;
       }
     }
   }

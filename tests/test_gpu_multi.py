@@ -61,6 +61,33 @@ def test_multi_matches_oracle(lms, length, slide):
     check_all(lms, batches, groups, d, w, "multi")
 
 
+def test_multi_wide_value_columns(lms):
+    """The persistent launch on batches with int64 and float64 value columns
+    next to int32 and float32 ones (staged records with 8-byte values ahead
+    of the pane), each batch against the oracle."""
+    aggs = [(COUNT, 0), (SUM, 4), (MIN, 4), (MAX, 2), (AVG, 5), (AVG, 3)]
+    batches = []
+    for i, n in enumerate([50000, 1, 120001, 777]):
+        rng = np.random.default_rng(300 + i)
+        ts = rng.integers(0, 20000, n, dtype=np.int64)
+        key = rng.integers(0, 900, n, dtype=np.int64)
+        val = rng.integers(-1000, 1000, n, dtype=np.int32)
+        f = rng.standard_normal(n).astype(np.float32)
+        v64 = rng.integers(-(1 << 40), 1 << 40, n, dtype=np.int64)
+        f64 = rng.standard_normal(n) * 1e6
+        batches.append([ts, key, val, f, v64, f64])
+    w = lms.Window(0, 3000, 1000, 0)
+    log("multi wide values")
+    groups, d, _ = lms.lms_window_agg_multi([to_dev(c) for c in batches], 1, w, aggs, PREDS)
+    torch.cuda.synchronize()
+    for b, cols in enumerate(batches):
+        got, cnt, status = result(groups, d, b)
+        assert status == 0, f"wide batch {b}: status {status}"
+        exp = oracle.window_agg(cols, 1, 0, w.length, w.slide, w.origin, aggs, PREDS)
+        assert cnt == len(exp["key"]), f"wide batch {b}"
+        assert_window_equal(got, exp, aggs, f"wide batch {b}")
+
+
 def test_multi_equals_single_calls(lms):
     log("multi vs single")
     batches = [batch_cols(200 + i, n) for i, n in enumerate([9000, 40000, 1, 65536])]

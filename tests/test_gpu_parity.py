@@ -203,12 +203,12 @@ def test_window_agg_eight_accumulators():
     assert_window_equal(got, exp, aggs, "eight")
 
 
-def wide_value_cols(seed, n):
+def wide_value_cols(seed, n, nkeys=3000):
     """ts, key, an int32 and a float32 value column, and an int64 and a
     float64 one (values below 2^40, so no sum wraps)."""
     rng = np.random.default_rng(seed)
     ts = rng.integers(0, 30000, n, dtype=np.int64)
-    key = rng.integers(0, 3000, n, dtype=np.int64)
+    key = rng.integers(0, nkeys, n, dtype=np.int64)
     v32 = rng.integers(-1000, 1000, n, dtype=np.int32)
     f32 = rng.standard_normal(n).astype(np.float32)
     v64 = rng.integers(-(1 << 40), 1 << 40, n, dtype=np.int64)
@@ -216,24 +216,26 @@ def wide_value_cols(seed, n):
     return [ts, key, v32, f32, v64, f64]
 
 
-@pytest.mark.parametrize("aggs,projs", [
+@pytest.mark.parametrize("aggs,projs,nkeys", [
     # six accumulators: two 8-byte values ahead of the pane in the staged
     # record, two 4-byte ones behind it (a 40-byte record)
-    ([(COUNT, 0), (SUM, 4), (MIN, 4), (MAX, 4), (AVG, 5), (SUM, 2), (AVG, 3)], []),
+    ([(COUNT, 0), (SUM, 4), (MIN, 4), (MAX, 4), (AVG, 5), (SUM, 2), (AVG, 3)], [], 3000),
     # four accumulators over 8-byte values only, one of them a projection of
     # the int64 column (an int64 result)
-    ([(SUM, 6), (AVG, 5), (MAX, 4), (COUNT, 0)], [(4, 3, 1)]),
+    ([(SUM, 6), (AVG, 5), (MAX, 4), (COUNT, 0)], [(4, 3, 1)], 3000),
     # an 8-byte value between 4-byte ones in the aggregate order
-    ([(MIN, 2), (MAX, 4), (AVG, 3)], []),
+    ([(MIN, 2), (MAX, 4), (AVG, 3)], [], 3000),
+    # five keys: partitions beyond the piece size, aggregated in pieces and merged
+    ([(COUNT, 0), (SUM, 4), (MIN, 4), (AVG, 5), (MAX, 2)], [], 5),
 ])
-def test_window_agg_wide_value_columns(aggs, projs):
+def test_window_agg_wide_value_columns(aggs, projs, nkeys):
     """Value columns of every width in one call: int64 and float64 values sit
     ahead of the pane in a staged record and int32 and float32 ones behind
     it, so each field of the record is read at its own word and half."""
     n = 200003
-    cols = wide_value_cols(41, n)
+    cols = wide_value_cols(41, n, nkeys)
     preds = [(2, LT, 600)]
-    log(f"wide values aggs={aggs} projs={projs}")
+    log(f"wide values aggs={aggs} projs={projs} nkeys={nkeys}")
     got, cnt, status = gpu_window_agg(cols, 1, 0, 5000, 1000, 0, aggs, preds, projs)
     assert status == 0
     exp = oracle.window_agg(cols, 1, 0, 5000, 1000, 0, aggs, preds, projs)

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from gpu_helpers import assert_window_equal, gpu_window_agg, log, to_dev
-from oracle import AVG, COUNT, GE, LE, LT, MAX, MIN, NE, SUM
+from oracle import AVG, COUNT, GE, GT, LE, LT, MAX, MIN, NE, SUM
 from paper_2111_04289_amd import datagen
 
 pytestmark = pytest.mark.gpu
@@ -113,6 +113,19 @@ def test_filter_project_all_and_none(lms):
         assert int(d[0]) == expect
         if expect:
             np.testing.assert_array_equal(out[1][:expect].cpu().numpy(), cols[2])
+
+
+def test_filter_project_wide_columns(lms):
+    """Predicates on a float64 (with NaNs) and an int64 column, float64 and
+    int64 columns kept, and an int64 projection that wraps: the 8-byte paths
+    of the predicate, the copy and the projection."""
+    n = 150001
+    cols = wide_value_cols(51, n)
+    cols[5][::89] = np.nan
+    log("filter_project wide columns")
+    m = _check_filter(lms, cols, to_dev(cols), [(5, GT, 0, -2e5), (4, LT, 1 << 39)], [0, 5, 4, 3],
+                      [(4, 1 << 30, 7), (2, -5, 1)])
+    assert 0 < m < n
 
 
 # ---------------------------------------------------------------- windowed group-by
@@ -234,7 +247,8 @@ def test_window_agg_wide_value_columns(aggs, projs, nkeys):
     it, so each field of the record is read at its own word and half."""
     n = 200003
     cols = wide_value_cols(41, n, nkeys)
-    preds = [(2, LT, 600)]
+    cols[5][::101] = np.nan
+    preds = [(2, LT, 600), (5, GT, 0, -1.5e6)]  # and a float64 predicate (NaN rows fail it)
     log(f"wide values aggs={aggs} projs={projs} nkeys={nkeys}")
     got, cnt, status = gpu_window_agg(cols, 1, 0, 5000, 1000, 0, aggs, preds, projs)
     assert status == 0

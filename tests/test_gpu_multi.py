@@ -61,11 +61,14 @@ def test_multi_matches_oracle(lms, length, slide):
     check_all(lms, batches, groups, d, w, "multi")
 
 
-def test_multi_wide_value_columns(lms):
+@pytest.mark.parametrize("aggs", [
+    [(COUNT, 0), (SUM, 4), (MIN, 4), (MAX, 2), (AVG, 5), (AVG, 3)],  # five accumulators
+    [(SUM, 2), (MIN, 2), (MAX, 2), (AVG, 3), (SUM, 4), (MIN, 4), (MAX, 4), (AVG, 5)],  # eight, the widest
+])
+def test_multi_wide_value_columns(lms, aggs):
     """The persistent launch on batches with int64 and float64 value columns
     next to int32 and float32 ones (staged records with 8-byte values ahead
     of the pane), each batch against the oracle."""
-    aggs = [(COUNT, 0), (SUM, 4), (MIN, 4), (MAX, 2), (AVG, 5), (AVG, 3)]
     batches = []
     for i, n in enumerate([50000, 1, 120001, 777]):
         rng = np.random.default_rng(300 + i)
@@ -77,7 +80,7 @@ def test_multi_wide_value_columns(lms):
         f64 = rng.standard_normal(n) * 1e6
         batches.append([ts, key, val, f, v64, f64])
     w = lms.Window(0, 3000, 1000, 0)
-    log("multi wide values")
+    log(f"multi wide values aggs={aggs}")
     groups, d, _ = lms.lms_window_agg_multi([to_dev(c) for c in batches], 1, w, aggs, PREDS)
     torch.cuda.synchronize()
     for b, cols in enumerate(batches):

@@ -321,7 +321,9 @@ int lms_window_agg_multi_launch(const lms_multi_config* cfg, void* workspace, lm
  * per CU, and (key, pane) slots of an aggregation workgroup's LDS table (1024
  * or 2048, the default; the smaller table fits two workgroups' LDS in a CU
  * and lowers the panes one key may hold, lms_window_agg_pane_limit).  Unset partition and piece sizes default to 8
- * and 4 rows per table slot.  Chosen by the project's autotuner; results never
+ * and 4 rows per table slot, except that a batch of fewer than 8 x 32 rows per
+ * slot targets 1/32 of its rows per partition (at least 2048), so that it
+ * spreads over 32 partitions.  Chosen by the project's autotuner; results never
  * depend on them. */
 typedef struct {
   int32_t chunk_rows;

@@ -321,6 +321,7 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan1(WinArgs a) {
 }
 
 constexpr int kMaxParts = 4096;  // partitions of one batch (make_plan's bound)
+constexpr int64_t kMinParts = 32;  // partitions a batch of 64K rows or more is spread over at least
 constexpr int kPlanTPB = 1024;   // threads of the planning workgroup: a few partitions each
 
 // Partition starts and the aggregation work items of one batch (one
@@ -2072,10 +2073,16 @@ Plan make_plan(int64_t n, int nval, int nacc) {
   else p.chunk = std::min<int64_t>(kMaxChunk, std::max<int64_t>(2048, next_pow2((n + 1023) / 1024)));
   p.g1 = (int)((n + p.chunk - 1) / p.chunk);
   // the LDS group table sets the scale: by default a partition targets 8 rows
-  // per table slot and an aggregation piece 4 (16384 and 8192 at 2048 slots)
+  // per table slot and an aggregation piece 4 (16384 and 8192 at 2048 slots);
+  // a batch too small to fill kMinParts partitions that way targets fewer rows
+  // per partition (down to 2048), so its items run on that many CUs at once
+  // instead of on a few: a micro-batch's latency is its longest item's
   p.eg = g_tuning.lds_groups > 0 ? g_tuning.lds_groups : 2048;
   p.ek = p.eg / 2;
-  const int64_t part_rows = g_tuning.part_rows > 0 ? g_tuning.part_rows : 8 * (int64_t)p.eg;
+  const int64_t part_rows = g_tuning.part_rows > 0
+                                ? g_tuning.part_rows
+                                : std::min<int64_t>(8 * (int64_t)p.eg,
+                                                    std::max<int64_t>(2048, (n + kMinParts - 1) / kMinParts));
   p.nparts = (int)std::min<int64_t>(kMaxParts, std::max<int64_t>(8, next_pow2((n + part_rows - 1) / part_rows)));
   p.pbits = ilog2(p.nparts);
   p.rs = g_tuning.piece_rows > 0 ? g_tuning.piece_rows : 4 * (int64_t)p.eg;
@@ -2103,7 +2110,7 @@ size_t carve_workspace(const Plan& p, void* base, WinArgs* a) {
   Item* items = c.take<Item>(p.max_items);
   uint32_t* pfill = c.take<uint32_t>(p.nparts);
   uint64_t* pmask = c.take<uint64_t>((size_t)(p.n + 63) / 64 + 1);
-  char* srec = c.take<char>((size_t)p.n * rec_bound(p.nval) + 8);  // + a word read past the last record
+  char* srec = c.take<char>((size_t)p.n * rec_bound(p.nval) + 8);  // + one spare word
   int64_t* pkey = c.take<int64_t>(p.n);
   uint32_t* ppane = c.take<uint32_t>(p.n);
   uint32_t* pcnt = c.take<uint32_t>(p.n);

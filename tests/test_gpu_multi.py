@@ -116,7 +116,7 @@ def test_multi_graph_replay(lms):
     batches = [batch_cols(300 + i, n) for i, n in enumerate(sizes)]
     dev = [to_dev(c) for c in batches]
     job = lms.MultiJob(1, w, AGGS, PREDS)
-    big = [batch_cols(600, 400000)]
+    big = [batch_cols(600, 1200000)]  # more partitions than any batch above (128 against 32)
     dbig = [to_dev(c) for c in big]
     job.reserve(job.workspace_bytes(dbig))  # the captured graph reads this workspace, so it never moves
     groups, d = job.prepare(dev)

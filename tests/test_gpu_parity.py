@@ -145,6 +145,50 @@ def test_config0_tumbling_exact():
     assert_window_equal(got, exp, aggs, "config0")
 
 
+@pytest.mark.parametrize("length,slide", [(1000, 0), (3000, 1000)])
+def test_window_agg_graph_replay(lms, length, slide):
+    """One call captured in a HIP graph (the plan is fixed by the batch size at
+    capture) and replayed on new data in the same input buffers, with eager
+    work between replays: every replay equals the oracle on its data."""
+    n = 65536
+    aggs = [(COUNT, 0), (SUM, 4), (MIN, 2), (AVG, 3)]
+    preds, projs = [(2, LT, 500)], [(2, 2, 0)]
+    w = lms.Window(0, length, slide, 0)
+    dev = to_dev(datagen.config0(n))
+    groups = lms.Groups(n * 3, aggs, dev[0].device)
+    d = torch.zeros(2, dtype=torch.int64, device=dev[0].device)
+    ws = lms.Workspace(dev[0].device)
+
+    def call():
+        lms.lms_window_agg(dev, 1, w, aggs, preds, projs, groups=groups, d_count=d, workspace=ws)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()  # sizes the workspace and sets kernel attributes before capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        call()
+    for rep in range(4):
+        log(f"window_agg graph replay {rep} len={length} slide={slide}")
+        cols = rand_cols(700 + rep, n, 1024, 10000, key64=False)  # the dtypes of the captured batch
+        for t, c in zip(dev, cols):
+            t.copy_(torch.from_numpy(c))
+        d.fill_(-1)
+        _ = (dev[2] * 3).sum().item()  # unrelated eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        cnt, status = [int(x) for x in d.cpu()]
+        assert status == 0
+        got = {"key": groups.key[:cnt].cpu().numpy(), "wstart": groups.wstart[:cnt].cpu().numpy(),
+               "aggs": [a[:cnt].cpu().numpy() for a in groups.aggs]}
+        exp = oracle.window_agg(cols, 1, 0, length, slide, 0, aggs, preds, projs)
+        assert cnt == len(exp["key"]) > 0
+        assert_window_equal(got, exp, aggs, f"graph replay {rep}")
+
+
 @pytest.mark.parametrize("n,length,slide,origin,key64,neg,nkeys,tspan", [
     (1, 10, 0, 0, True, False, 5, 100),
     (1000, 10, 3, 5, True, True, 7, 200),

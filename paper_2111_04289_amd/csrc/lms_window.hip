@@ -485,6 +485,38 @@ __global__ __launch_bounds__(kScanTPB) void k_wa_scan2(WinArgs a) {
   scan2_part(a, blockIdx.x, scratch);
 }
 
+// The three steps above in one workgroup, for a batch of at most kSmallChunks
+// chunks (a micro-batch, whose three launches would cost more than their
+// work): each wave takes one partition at a time, one chunk per lane, and sums
+// (rows per partition) or scans (write offsets) the partition's chunk counts
+// with shuffles; the plan sits between the two, as in the separate launches.
+constexpr int kSmallChunks = 64;
+
+__global__ __launch_bounds__(kPlanTPB) void k_wa_scans(WinArgs a) {
+  __shared__ uint32_t r[kMaxParts], st[kMaxParts], kc[kMaxParts], base[kMaxParts];
+  __shared__ uint32_t scratch[kPlanTPB / 64 + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int p = wave; p < a.nparts; p += kPlanTPB / 64) {
+    uint32_t s = lane < a.g1 ? a.H[(size_t)p * a.g1 + lane] : 0u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += (uint32_t)__shfl_xor((int)s, d, 64);
+    if (lane == 0) a.Rp[p] = s;
+  }
+  __syncthreads();
+  plan_items(a, r, st, kc, base, scratch);  // ends with a barrier: every partition start is set
+  for (int p = wave; p < a.nparts; p += kPlanTPB / 64) {
+    const uint32_t h = lane < a.g1 ? a.H[(size_t)p * a.g1 + lane] : 0u;
+    uint32_t x = h;  // inclusive scan over the lanes
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = (uint32_t)__shfl_up((int)x, d, 64);
+      if (lane >= d) x += y;
+    }
+    if (lane < a.g1) a.Off[(size_t)p * a.g1 + lane] = a.pinfo[p].start + x - h;
+  }
+  save_args(a);
+}
+
 // Raw bits of staged value column v (int64, or the float's own bits) for rows
 // idx[u] where ld[u], U at a time (see load_i64_rows).
 template <int U>
@@ -2389,9 +2421,13 @@ extern "C" int lms_window_agg(const lms_batch* in, const lms_pred* preds, int32_
   if (in->nrows > 0) {
     const size_t plds = (size_t)p.nparts * 4;
     LMS_LAUNCH("k_wa_hist", k_wa_hist, dim3(xcd_slots(p.g1)), dim3(kScanTPB), hist_lds(p.nparts, p.chunk), st, a);
-    LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
-    LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kPlanTPB), 0, st, a);
-    LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
+    if (p.g1 <= kSmallChunks) {
+      LMS_LAUNCH("k_wa_scans", k_wa_scans, dim3(1), dim3(kPlanTPB), 0, st, a);
+    } else {
+      LMS_LAUNCH("k_wa_scan1", k_wa_scan1, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
+      LMS_LAUNCH("k_wa_scanp", k_wa_scanp, dim3(1), dim3(kPlanTPB), 0, st, a);
+      LMS_LAUNCH("k_wa_scan2", k_wa_scan2, dim3(p.nparts), dim3(kScanTPB), 0, st, a);
+    }
     // loops over accumulators are unrolled to the smallest bound covering them
     const int ma = acc_bound(a.nacc);
     if (ma == 2) launch_tail<2>(p, a, plds, st);

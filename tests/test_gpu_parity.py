@@ -211,6 +211,21 @@ def test_window_agg_parity(n, length, slide, origin, key64, neg, nkeys, tspan):
     assert_window_equal(got, exp, aggs, f"n={n}")
 
 
+@pytest.mark.parametrize("n", [131072, 131073])
+@pytest.mark.parametrize("length,slide", [(1000, 0), (5000, 1000)])
+def test_window_agg_scan_paths_at_the_chunk_threshold(n, length, slide):
+    """64 chunks of 2048 rows take the one-workgroup scans, 65 chunks the three
+    scan launches; both against the oracle."""
+    log(f"scan paths n={n} len={length} slide={slide}")
+    cols = rand_cols(n % 7, n, 3000, 20000)
+    preds, projs = [(2, LT, 300)], [(2, 3, -7)]
+    aggs = [(COUNT, 0), (SUM, 4), (MAX, 2), (AVG, 3)]
+    got, cnt, status = gpu_window_agg(cols, 1, 0, length, slide, 0, aggs, preds, projs)
+    assert status == 0
+    exp = oracle.window_agg(cols, 1, 0, length, slide, 0, aggs, preds, projs)
+    assert cnt == len(exp["key"]) > 0
+    assert_window_equal(got, exp, aggs, f"n={n}")
+
 @pytest.mark.parametrize("tmax", [640, 650, 10])
 def test_window_agg_pane_span_at_mask_width(tmax):
     """Panes 0..63 (span 63), 0..64 (span 64) and a single pane: the sliding

@@ -33,7 +33,7 @@ SPACE = {
     "lds_groups": [0, 1024],
     "part_rows": [0, 4096, 8192, 32768],
     "piece_rows": [0, 2048, 4096, 16384],
-    "grid_per_cu": [0, 2, 8],
+    "grid_per_cu": [0, 2, 5, 8],
 }
 # Coordinates of the descent.  Partition and piece sizes default to multiples of
 # the LDS table size, so the table-size coordinate moves all three coherently;
@@ -87,7 +87,7 @@ def _batched(torch, dev, rows, nbatch=256, seed=11):
     rng = np.random.default_rng(seed)
     hi = min(8 << 20, rows)
     sizes = np.exp(rng.uniform(np.log(1024), np.log(hi), nbatch)).astype(np.int64)
-    offs = [int(rng.integers(0, rows - s + 1)) for s in sizes]
+    offs = [4 * int(rng.integers(0, (rows - s) // 4 + 1)) for s in sizes]  # 16-byte aligned, as separate buffers
     batches = [[c[o:o + int(s)] for c in cols] for o, s in zip(offs, sizes)]
     aggs = [(lms.COUNT, 0), (lms.SUM, 4)]
     job = lms.MultiJob(1, lms.Window(0, 1000, 0, 0), aggs, [(2, lms.LT, 500)], [(2, 2, 0)], device=dev)
